@@ -1,0 +1,764 @@
+/*
+ * mcrt_oracle.c -- plain serial FP64 oracle of the Monte Carlo photon-packet
+ * life cycle described in the hybrid-parallel SKIRT paper, Section 3.2
+ * ("Stellar emission phase"): each packet is launched, propagated through the
+ * dust grid, loses luminosity continuously by absorption into the
+ * per-cell, per-wavelength absorbed-luminosity table (Section 5.2, the
+ * DustSystem::absorb / ParallelTable description), is forced to interact,
+ * peels off luminosity towards every instrument at emission (Fig. 2 caption)
+ * and at every scattering event, and is followed until only a negligible part
+ * of its launch luminosity remains.
+ *
+ * TEST INFRASTRUCTURE ONLY (see mcrt_oracle.h).  The paper names the
+ * acceleration techniques (peel-off, continuous absorption, forced
+ * scattering; Section 1) without giving their formulas; this file writes out
+ * the standard estimator those names denote, step by step in the order the
+ * method takes them, with no blocking, fusion or reordering.  The readings
+ * taken where the paper is silent are listed with the design notes.
+ *
+ * Compiled with -O2 -ffp-contract=off (no fused multiply-add), FP64 only.
+ */
+#include "mcrt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11, Section 4): 10 rounds of the Philox S-P network  */
+/* on a 128-bit counter with a 64-bit key, the key bumped by the Weyl        */
+/* constants between rounds.                                                 */
+/* ------------------------------------------------------------------------ */
+
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t *hi, uint32_t *lo)
+{
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    *hi = (uint32_t)(p >> 32);
+    *lo = (uint32_t)p;
+}
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint32_t hi0, lo0, hi1, lo1;
+        mulhilo32(M0, c0, &hi0, &lo0);
+        mulhilo32(M1, c2, &hi1, &lo1);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Slot s of a packet's stream: Philox block floor(s/2), output words
+ * 2(s mod 2) (high) and 2(s mod 2)+1 (low).  Counter = (block, packet,
+ * wavelength, model); key = (low 32 bits of the seed, high 32 bits). */
+static void slot_words(uint64_t seed, uint32_t packet, uint32_t lambda, uint32_t model,
+                       uint32_t slot, uint32_t *hi, uint32_t *lo)
+{
+    uint32_t ctr[4] = {slot / 2u, packet, lambda, model};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    or_philox4x32_10(ctr, key, out);
+    uint32_t w = 2u * (slot % 2u);
+    *hi = out[w];
+    *lo = out[w + 1];
+}
+
+/* Uniform in the open interval (0, 1) from the top 52 bits of the slot's
+ * 64-bit word: ((w >> 12) + 1/2) * 2^-52. */
+double or_uniform64(uint64_t seed, uint32_t packet, uint32_t lambda, uint32_t model, uint32_t slot)
+{
+    uint32_t hi, lo;
+    slot_words(seed, packet, lambda, model, slot, &hi, &lo);
+    uint64_t w = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
+
+/* Single-precision variant: ((hi >> 9) + 1/2) * 2^-23. */
+float or_uniform32(uint64_t seed, uint32_t packet, uint32_t lambda, uint32_t model, uint32_t slot)
+{
+    uint32_t hi, lo;
+    slot_words(seed, packet, lambda, model, slot, &hi, &lo);
+    return ((float)(hi >> 9) + 0.5f) * 0x1p-23f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: the dust grid and the ray march.                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const or_scene *s;
+    /* octree derived data */
+    int depth;          /* maximum leaf depth D */
+    int64_t lattice;    /* 2^D */
+    int64_t *leaf_of_node; /* leaf index (depth-first order) or -1 */
+} geom;
+
+typedef struct {
+    int64_t *cell;
+    double *tend;       /* ray parameter at the end of the segment */
+    int64_t n, cap;
+    double t0;          /* ray parameter where the first segment starts */
+} seglist;
+
+static int seg_push(seglist *sl, int64_t cell, double tend)
+{
+    if (sl->n == sl->cap) {
+        int64_t nc = sl->cap ? 2 * sl->cap : 256;
+        int64_t *c = (int64_t *)realloc(sl->cell, (size_t)nc * sizeof(int64_t));
+        if (!c) return -1;
+        sl->cell = c;
+        double *t = (double *)realloc(sl->tend, (size_t)nc * sizeof(double));
+        if (!t) return -1;
+        sl->tend = t;
+        sl->cap = nc;
+    }
+    sl->cell[sl->n] = cell;
+    sl->tend[sl->n] = tend;
+    sl->n++;
+    return 0;
+}
+
+static void seg_free(seglist *sl)
+{
+    free(sl->cell);
+    free(sl->tend);
+    memset(sl, 0, sizeof(*sl));
+}
+
+/* Builds the octree derived data: maximum depth and depth-first leaf order
+ * (children visited in the order c = bx + 2 by + 4 bz). */
+static int geom_init(geom *g, const or_scene *s)
+{
+    memset(g, 0, sizeof(*g));
+    g->s = s;
+    if (s->grid_type != OR_GRID_OCTREE) return 0;
+    int64_t nn = s->n_nodes;
+    g->leaf_of_node = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    int64_t *stack_node = (int64_t *)malloc((size_t)(nn + 8) * sizeof(int64_t));
+    int *stack_level = (int *)malloc((size_t)(nn + 8) * sizeof(int));
+    if (!g->leaf_of_node || !stack_node || !stack_level) {
+        free(stack_node);
+        free(stack_level);
+        return -1;
+    }
+    for (int64_t i = 0; i < nn; ++i) g->leaf_of_node[i] = -1;
+    int64_t top = 0, next_leaf = 0;
+    int maxdepth = 0;
+    stack_node[top] = 0;
+    stack_level[top] = 0;
+    top++;
+    while (top > 0) {
+        top--;
+        int64_t node = stack_node[top];
+        int level = stack_level[top];
+        int32_t fc = s->first_child[node];
+        if (fc < 0) {
+            g->leaf_of_node[node] = next_leaf++;
+            if (level > maxdepth) maxdepth = level;
+        } else {
+            for (int c = 7; c >= 0; --c) {
+                stack_node[top] = (int64_t)fc + c;
+                stack_level[top] = level + 1;
+                top++;
+            }
+        }
+    }
+    free(stack_node);
+    free(stack_level);
+    g->depth = maxdepth;
+    g->lattice = (int64_t)1 << maxdepth;
+    return next_leaf == s->n_cells ? 0 : -1;
+}
+
+static void geom_free(geom *g)
+{
+    free(g->leaf_of_node);
+    g->leaf_of_node = NULL;
+}
+
+/* Index of the grid slice containing coordinate p along an axis with origin
+ * lo, spacing d and n slices; a point exactly on a plane that the ray leaves
+ * towards lower coordinates belongs to the slice below the plane. */
+static int64_t slice_index(double p, double lo, double d, int64_t n, double k)
+{
+    int64_t i = (int64_t)floor((p - lo) / d);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    if (p == lo + (double)i * d && k < 0.0) i -= 1;
+    return i;
+}
+
+/* Finds where the ray r + t k (t >= 0) starts inside the box: t0 and the
+ * slice indices along each axis (spacing d[a], n[a] slices).  Returns 0 if
+ * the ray misses the box or leaves it immediately. */
+static int ray_start(const double box[6], const double d[3], const int64_t n[3],
+                     const double r[3], const double k[3], double *t0, int64_t idx[3])
+{
+    const double *lo = box, *hi = box + 3;
+    int inside = 1;
+    for (int a = 0; a < 3; ++a)
+        if (!(r[a] >= lo[a] && r[a] <= hi[a])) inside = 0;
+    if (inside) {
+        *t0 = 0.0;
+        for (int a = 0; a < 3; ++a) idx[a] = slice_index(r[a], lo[a], d[a], n[a], k[a]);
+    } else {
+        double tn = -INFINITY, tf = INFINITY;
+        int entry = -1;
+        for (int a = 0; a < 3; ++a) {
+            if (k[a] == 0.0) {
+                if (r[a] < lo[a] || r[a] > hi[a]) return 0;
+            } else {
+                double t1 = (lo[a] - r[a]) / k[a];
+                double t2 = (hi[a] - r[a]) / k[a];
+                double near = t1 < t2 ? t1 : t2;
+                double far = t1 < t2 ? t2 : t1;
+                if (near > tn) {
+                    tn = near;
+                    entry = a;
+                }
+                if (far < tf) tf = far;
+            }
+        }
+        if (entry < 0 || tn > tf || tf < 0.0 || tn < 0.0) return 0;
+        *t0 = tn;
+        for (int a = 0; a < 3; ++a) {
+            if (a == entry) {
+                idx[a] = k[a] > 0.0 ? 0 : n[a] - 1;
+            } else {
+                double p = r[a] + tn * k[a];
+                idx[a] = slice_index(p, lo[a], d[a], n[a], k[a]);
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a)
+        if (idx[a] < 0 || idx[a] >= n[a]) return 0;
+    return 1;
+}
+
+/* Ray parameter where the ray crosses the plane lo + j d of axis a. */
+static double plane_t(double lo, double d, int64_t j, double r, double k)
+{
+    return (lo + (double)j * d - r) / k;
+}
+
+/* Cartesian grid: 3-D digital differential analyser.  At each step the axis
+ * whose next plane is nearest is stepped (ties to the lowest axis); plane
+ * crossings are recomputed from the original ray origin every step. */
+static int march_cartesian(const geom *g, const double r[3], const double k[3], seglist *sl)
+{
+    const or_scene *s = g->s;
+    int64_t n[3] = {s->n[0], s->n[1], s->n[2]};
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = (s->box[3 + a] - s->box[a]) / (double)n[a];
+    sl->n = 0;
+    sl->t0 = 0.0;
+    int64_t idx[3];
+    double t;
+    if (!ray_start(s->box, d, n, r, k, &t, idx)) return 0;
+    sl->t0 = t;
+    for (;;) {
+        double tn[3];
+        for (int a = 0; a < 3; ++a) {
+            if (k[a] > 0.0) tn[a] = plane_t(s->box[a], d[a], idx[a] + 1, r[a], k[a]);
+            else if (k[a] < 0.0) tn[a] = plane_t(s->box[a], d[a], idx[a], r[a], k[a]);
+            else tn[a] = INFINITY;
+        }
+        int am = 0;
+        if (tn[1] < tn[am]) am = 1;
+        if (tn[2] < tn[am]) am = 2;
+        double te = tn[am] > t ? tn[am] : t;
+        int64_t cell = idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
+        if (seg_push(sl, cell, te)) return -1;
+        t = te;
+        idx[am] += k[am] > 0.0 ? 1 : -1;
+        if (idx[am] < 0 || idx[am] >= n[am]) break;
+    }
+    return 0;
+}
+
+/* Octree: walk on the integer lattice of the deepest level.  The current
+ * lattice point is located by descending from the root; the leaf's exit
+ * plane is found as in the Cartesian march; the next lattice point lies just
+ * across the exit face, with the in-face coordinates taken from the exit
+ * point and clamped into the current leaf. */
+static int march_octree(const geom *g, const double r[3], const double k[3], seglist *sl)
+{
+    const or_scene *s = g->s;
+    int64_t N = g->lattice;
+    int64_t n[3] = {N, N, N};
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = (s->box[3 + a] - s->box[a]) / (double)N;
+    sl->n = 0;
+    sl->t0 = 0.0;
+    int64_t c[3];
+    double t;
+    if (!ray_start(s->box, d, n, r, k, &t, c)) return 0;
+    sl->t0 = t;
+    int64_t guard = 16 * 3 * N + 64;
+    for (int64_t step = 0; step < guard; ++step) {
+        int64_t node = 0;
+        int level = 0;
+        while (s->first_child[node] >= 0) {
+            int bit = g->depth - 1 - level;
+            int64_t child = ((c[0] >> bit) & 1) + 2 * ((c[1] >> bit) & 1) + 4 * ((c[2] >> bit) & 1);
+            node = (int64_t)s->first_child[node] + child;
+            level++;
+        }
+        int64_t size = (int64_t)1 << (g->depth - level);
+        int64_t o[3];
+        for (int a = 0; a < 3; ++a) o[a] = c[a] - (c[a] % size);
+        double tn[3];
+        for (int a = 0; a < 3; ++a) {
+            if (k[a] > 0.0) tn[a] = plane_t(s->box[a], d[a], o[a] + size, r[a], k[a]);
+            else if (k[a] < 0.0) tn[a] = plane_t(s->box[a], d[a], o[a], r[a], k[a]);
+            else tn[a] = INFINITY;
+        }
+        int am = 0;
+        if (tn[1] < tn[am]) am = 1;
+        if (tn[2] < tn[am]) am = 2;
+        double te = tn[am] > t ? tn[am] : t;
+        if (seg_push(sl, g->leaf_of_node[node], te)) return -1;
+        t = te;
+        int64_t nc[3];
+        for (int a = 0; a < 3; ++a) {
+            if (a == am) {
+                nc[a] = k[a] > 0.0 ? o[a] + size : o[a] - 1;
+            } else {
+                double p = r[a] + te * k[a];
+                int64_t q = (int64_t)floor((p - s->box[a]) / d[a]);
+                if (q < o[a]) q = o[a];
+                if (q > o[a] + size - 1) q = o[a] + size - 1;
+                nc[a] = q;
+            }
+        }
+        if (nc[am] < 0 || nc[am] >= N) return 0;
+        c[0] = nc[0]; c[1] = nc[1]; c[2] = nc[2];
+    }
+    return -2; /* the walk did not leave the grid: malformed octree */
+}
+
+static int march(const geom *g, const double r[3], const double k[3], seglist *sl)
+{
+    if (g->s->grid_type == OR_GRID_OCTREE) return march_octree(g, r, k, sl);
+    return march_cartesian(g, r, k, sl);
+}
+
+int64_t or_march(const or_scene *scene, const double r[3], const double k[3],
+                 int64_t *cells, double *lengths, int64_t max_seg)
+{
+    geom g;
+    if (geom_init(&g, scene)) {
+        geom_free(&g);
+        return -1;
+    }
+    seglist sl;
+    memset(&sl, 0, sizeof(sl));
+    int rc = march(&g, r, k, &sl);
+    int64_t n = sl.n;
+    if (rc || n > max_seg) {
+        n = -1;
+    } else {
+        double prev = sl.t0;
+        for (int64_t i = 0; i < n; ++i) {
+            cells[i] = sl.cell[i];
+            lengths[i] = sl.tend[i] - prev;
+            prev = sl.tend[i];
+        }
+    }
+    seg_free(&sl);
+    geom_free(&g);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase function and direction sampling.                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Henyey-Greenstein phase function, normalised to average 1 over the sphere. */
+double or_hg_phase(double g, double mu)
+{
+    double num = 1.0 - g * g;
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return num / (den * sqrt(den));
+}
+
+/* Inverse-CDF sample of the cosine of the HG scattering angle. */
+double or_hg_sample(double g, double u)
+{
+    double mu;
+    if (fabs(g) >= 1e-6) {
+        double q = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+        mu = (1.0 + g * g - q * q) / (2.0 * g);
+    } else {
+        mu = 2.0 * u - 1.0;
+    }
+    if (mu < -1.0) mu = -1.0;
+    if (mu > 1.0) mu = 1.0;
+    return mu;
+}
+
+/* Direction at polar cosine mu and azimuth phi about k.  The azimuth is
+ * measured from the plane of k and the z axis; when k is within 0.00447 rad
+ * of the z axis (|k_z| >= 0.99999) the x axis serves instead, applying the
+ * same formula to the cyclically permuted components (y, z, x). */
+static void rotate_about_pole(double a, double b, double c, double mu, double st,
+                              double cp, double sp, double *x, double *y, double *z)
+{
+    double s = sqrt(1.0 - c * c);
+    *x = mu * a + st * (a * c * cp - b * sp) / s;
+    *y = mu * b + st * (b * c * cp + a * sp) / s;
+    *z = mu * c - st * s * cp;
+}
+
+void or_rotate(const double k[3], double mu, double phi, double out[3])
+{
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double cp = cos(phi), sp = sin(phi);
+    double x, y, z;
+    if (fabs(k[2]) < 0.99999) {
+        rotate_about_pole(k[0], k[1], k[2], mu, st, cp, sp, &x, &y, &z);
+    } else {
+        double py, pz, px;
+        rotate_about_pole(k[1], k[2], k[0], mu, st, cp, sp, &py, &pz, &px);
+        x = px;
+        y = py;
+        z = pz;
+    }
+    double nrm = sqrt(x * x + y * y + z * z);
+    out[0] = x / nrm;
+    out[1] = y / nrm;
+    out[2] = z / nrm;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The packet life cycle.                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double kobs[3], ex[3], ey[3];
+    double fovx, fovy, inv4pid2;
+    int64_t nx, ny;
+    int64_t offset; /* first element of this instrument in the image array */
+} instr;
+
+typedef struct {
+    /* per-packet second-moment scratch: dense accumulators with touched lists */
+    double *acc;
+    int64_t *touched;
+    int64_t ntouched;
+    double *m2;
+} moment_buf;
+
+/* Every contribution is non-negative, so an element is untouched exactly
+ * while its accumulator is zero; zero contributions are skipped. */
+static void moment_add(moment_buf *mb, int64_t idx, double v)
+{
+    if (!mb->m2 || v == 0.0) return;
+    if (mb->acc[idx] == 0.0) mb->touched[mb->ntouched++] = idx;
+    mb->acc[idx] += v;
+}
+
+static void moment_flush(moment_buf *mb)
+{
+    if (!mb->m2) return;
+    for (int64_t i = 0; i < mb->ntouched; ++i) {
+        int64_t idx = mb->touched[i];
+        mb->m2[idx] += mb->acc[idx] * mb->acc[idx];
+        mb->acc[idx] = 0.0;
+    }
+    mb->ntouched = 0;
+}
+
+typedef struct {
+    const or_scene *s;
+    geom g;
+    instr *ins;
+    seglist sl;
+    or_out *out;
+    moment_buf mt, mi;
+    uint64_t seed;
+    uint32_t model;
+} runctx;
+
+/* Optical depth from r along k to the grid boundary. */
+static int optical_depth(runctx *c, const double r[3], const double k[3], double kappa, double *tau)
+{
+    int rc = march(&c->g, r, k, &c->sl);
+    if (rc) return rc;
+    double prev = c->sl.t0, sum = 0.0;
+    for (int64_t n = 0; n < c->sl.n; ++n) {
+        double ds = c->sl.tend[n] - prev;
+        prev = c->sl.tend[n];
+        sum += kappa * (double)c->s->density[c->sl.cell[n]] * ds;
+    }
+    c->out->stats.peel_cells += (uint64_t)c->sl.n;
+    *tau = sum;
+    return 0;
+}
+
+/* Peel-off: the luminosity lum, weighted by the probability per unit solid
+ * angle (phase, normalised to average 1) of leaving towards the observer and
+ * by the transmission exp(-tau) along the way, lands as flux
+ * lum * phase * exp(-tau) / (4 pi d^2) in the pixel that r projects onto. */
+static int peel(runctx *c, int ell, const double r[3], double lum, double phase,
+                double kappa, int j)
+{
+    const instr *in = &c->ins[j];
+    double tau;
+    int rc = optical_depth(c, r, in->kobs, kappa, &tau);
+    if (rc) return rc;
+    if (tau >= c->s->tau_peel_max) {
+        c->out->stats.peel_dropped++;
+        return 0;
+    }
+    double x = r[0] * in->ex[0] + r[1] * in->ex[1] + r[2] * in->ex[2];
+    double y = r[0] * in->ey[0] + r[1] * in->ey[1] + r[2] * in->ey[2];
+    double px = floor((x + 0.5 * in->fovx) / (in->fovx / (double)in->nx));
+    double py = floor((y + 0.5 * in->fovy) / (in->fovy / (double)in->ny));
+    if (px < 0.0 || px >= (double)in->nx || py < 0.0 || py >= (double)in->ny) return 0;
+    double flux = lum * phase * exp(-tau) * in->inv4pid2;
+    int64_t idx = in->offset + ((int64_t)ell * in->ny + (int64_t)py) * in->nx + (int64_t)px;
+    c->out->images[idx] += flux;
+    moment_add(&c->mi, idx, flux);
+    c->out->stats.peel_adds++;
+    return 0;
+}
+
+static double source_phase(const or_scene *s, const double kobs[3])
+{
+    if (s->source_type == OR_SRC_POINT_ANISO) return 2.0 * fabs(kobs[2]);
+    return 1.0;
+}
+
+static int one_packet(runctx *c, int ell, uint32_t id, double L0)
+{
+    const or_scene *s = c->s;
+    or_out *o = c->out;
+    const double kappa = s->kappa[ell], albedo = s->albedo[ell], g = s->hg_g[ell];
+#define U(slot) or_uniform64(c->seed, id, (uint32_t)ell, c->model, (uint32_t)(slot))
+    /* launch */
+    double r[3], k[3];
+    if (s->source_type == OR_SRC_EXPDISK) {
+        double R = -s->disk_hR * log(U(0) * U(1));
+        double phi = 2.0 * OR_PI * U(2);
+        double z = s->disk_zs * atanh(2.0 * U(3) - 1.0);
+        r[0] = R * cos(phi);
+        r[1] = R * sin(phi);
+        r[2] = z;
+    } else {
+        r[0] = s->src_pos[0];
+        r[1] = s->src_pos[1];
+        r[2] = s->src_pos[2];
+    }
+    double mu;
+    if (s->source_type == OR_SRC_POINT_ANISO) {
+        double u5 = U(5);
+        mu = u5 < 0.5 ? sqrt(2.0 * u5) : -sqrt(2.0 * u5 - 1.0);
+    } else {
+        mu = 2.0 * U(5) - 1.0;
+    }
+    double phi = 2.0 * OR_PI * U(6);
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    k[0] = st * cos(phi);
+    k[1] = st * sin(phi);
+    k[2] = mu;
+    o->energy[0] += L0;
+    o->stats.packets++;
+    /* emission peel-off */
+    for (int j = 0; j < s->n_ins; ++j) {
+        int rc = peel(c, ell, r, L0, source_phase(s, c->ins[j].kobs), kappa, j);
+        if (rc) return rc;
+    }
+    double L = L0;
+    int64_t e = 1;
+    for (;;) {
+        /* propagation to the boundary with continuous absorption */
+        int rc = march(&c->g, r, k, &c->sl);
+        if (rc) return rc;
+        o->stats.prop_cells += (uint64_t)c->sl.n;
+        const double wabs = (1.0 - albedo) * L;
+        double E = 1.0, tau = 0.0, prev = c->sl.t0;
+        for (int64_t n = 0; n < c->sl.n; ++n) {
+            int64_t m = c->sl.cell[n];
+            double ds = c->sl.tend[n] - prev;
+            prev = c->sl.tend[n];
+            double dtau = kappa * (double)s->density[m] * ds;
+            double x = -expm1(-dtau);
+            double A = wabs * E * x;
+            int64_t ti = m * s->n_lambda + ell;
+            o->table[ti] += A;
+            moment_add(&c->mt, ti, A);
+            o->energy[1] += A;
+            E = E * (1.0 - x);
+            tau = tau + dtau;
+        }
+        const double Epath = E;
+        o->energy[2] += L * Epath;
+        if (c->sl.n == 0 || albedo == 0.0 || tau == 0.0) break;
+        /* scattered luminosity and termination */
+        double Ls = albedo * L * (1.0 - Epath);
+        if (Ls < s->w_min * L0) {
+            o->energy[3] += Ls;
+            break;
+        }
+        /* forced interaction point */
+        double tau_int = -log1p(-U(8 * e + 0) * (1.0 - Epath));
+        int64_t nstar = -1, nlast = -1;
+        double taucum = 0.0, taustar_prev = 0.0, taulast_prev = 0.0;
+        prev = c->sl.t0;
+        double start_star = 0.0, start_last = 0.0;
+        for (int64_t n = 0; n < c->sl.n; ++n) {
+            int64_t m = c->sl.cell[n];
+            double ds = c->sl.tend[n] - prev;
+            double dtau = kappa * (double)s->density[m] * ds;
+            double tprev = taucum;
+            taucum = taucum + dtau;
+            if (dtau > 0.0) {
+                nlast = n;
+                taulast_prev = tprev;
+                start_last = prev;
+            }
+            if (taucum >= tau_int) {
+                nstar = n;
+                taustar_prev = tprev;
+                start_star = prev;
+                break;
+            }
+            prev = c->sl.tend[n];
+        }
+        if (nstar < 0) {
+            nstar = nlast;
+            taustar_prev = taulast_prev;
+            start_star = start_last;
+        }
+        {
+            int64_t m = c->sl.cell[nstar];
+            double ds = c->sl.tend[nstar] - start_star;
+            double inside = (tau_int - taustar_prev) / (kappa * (double)s->density[m]);
+            if (inside < 0.0) inside = 0.0;
+            if (inside > ds) inside = ds;
+            double dist = start_star + inside;
+            r[0] = r[0] + k[0] * dist;
+            r[1] = r[1] + k[1] * dist;
+            r[2] = r[2] + k[2] * dist;
+        }
+        o->stats.events++;
+        /* scattering peel-off */
+        for (int j = 0; j < s->n_ins; ++j) {
+            const double *ko = c->ins[j].kobs;
+            double cosang = k[0] * ko[0] + k[1] * ko[1] + k[2] * ko[2];
+            rc = peel(c, ell, r, Ls, or_hg_phase(g, cosang), kappa, j);
+            if (rc) return rc;
+        }
+        /* new direction */
+        double mus = or_hg_sample(g, U(8 * e + 1));
+        double phis = 2.0 * OR_PI * U(8 * e + 2);
+        double kn[3];
+        or_rotate(k, mus, phis, kn);
+        k[0] = kn[0];
+        k[1] = kn[1];
+        k[2] = kn[2];
+        L = Ls;
+        e = e + 1;
+        if (e > s->event_cap) {
+            o->energy[3] += L;
+            o->stats.capped++;
+            break;
+        }
+    }
+#undef U
+    moment_flush(&c->mt);
+    moment_flush(&c->mi);
+    return 0;
+}
+
+static void instruments_init(const or_scene *s, instr *ins)
+{
+    int64_t off = 0;
+    for (int j = 0; j < s->n_ins; ++j) {
+        const double *gm = s->ins_geom + 5 * j;
+        double i = gm[0] * OR_PI / 180.0, a = gm[1] * OR_PI / 180.0;
+        double si = sin(i), ci = cos(i), sa = sin(a), ca = cos(a);
+        instr *in = &ins[j];
+        in->kobs[0] = si * ca;
+        in->kobs[1] = si * sa;
+        in->kobs[2] = ci;
+        in->ex[0] = -sa;
+        in->ex[1] = ca;
+        in->ex[2] = 0.0;
+        in->ey[0] = -ci * ca;
+        in->ey[1] = -ci * sa;
+        in->ey[2] = si;
+        in->fovx = gm[3];
+        in->fovy = gm[4];
+        in->inv4pid2 = 1.0 / (4.0 * OR_PI * gm[2] * gm[2]);
+        in->nx = s->ins_npix[2 * j];
+        in->ny = s->ins_npix[2 * j + 1];
+        in->offset = off;
+        off += (int64_t)s->n_lambda * in->nx * in->ny;
+    }
+}
+
+int or_run(const or_scene *s, uint64_t n_per_lambda, uint64_t first_id,
+           uint64_t count, uint64_t seed, uint32_t model, or_out *out)
+{
+    if (!s || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
+    if (first_id + count > 0xffffffffull + 1ull) return -1;
+    if (s->n_lambda <= 0 || s->n_cells <= 0 || s->n_ins < 0) return -1;
+    runctx c;
+    memset(&c, 0, sizeof(c));
+    c.s = s;
+    c.out = out;
+    c.seed = seed;
+    c.model = model;
+    if (geom_init(&c.g, s)) {
+        geom_free(&c.g);
+        return -2;
+    }
+    c.ins = (instr *)calloc((size_t)(s->n_ins > 0 ? s->n_ins : 1), sizeof(instr));
+    instruments_init(s, c.ins);
+    int64_t ntab = s->n_cells * s->n_lambda;
+    int64_t nimg = 0;
+    for (int j = 0; j < s->n_ins; ++j) nimg += (int64_t)s->n_lambda * c.ins[j].nx * c.ins[j].ny;
+    if (out->table_m2) {
+        c.mt.m2 = out->table_m2;
+        c.mt.acc = (double *)calloc((size_t)ntab, sizeof(double));
+        c.mt.touched = (int64_t *)malloc((size_t)ntab * sizeof(int64_t));
+    }
+    if (out->image_m2 && nimg > 0) {
+        c.mi.m2 = out->image_m2;
+        c.mi.acc = (double *)calloc((size_t)nimg, sizeof(double));
+        c.mi.touched = (int64_t *)malloc((size_t)nimg * sizeof(int64_t));
+    }
+    int rc = 0;
+    for (int ell = 0; ell < s->n_lambda && rc == 0; ++ell) {
+        double L0 = s->lum[ell] / (double)n_per_lambda;
+        for (uint64_t i = first_id; i < first_id + count; ++i) {
+            rc = one_packet(&c, ell, (uint32_t)i, L0);
+            if (rc) break;
+        }
+    }
+    free(c.mt.acc);
+    free(c.mt.touched);
+    free(c.mi.acc);
+    free(c.mi.touched);
+    free(c.ins);
+    seg_free(&c.sl);
+    geom_free(&c.g);
+    return rc ? -3 : 0;
+}

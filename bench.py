@@ -1,0 +1,213 @@
+"""Throughput benchmark of the photon-packet life cycle on one MI355X.
+
+Workload (default): the exponential-disk galaxy -- 256^3 Cartesian grid, 64
+log-spaced wavelengths 0.1-1000 um with power-law opacity and albedo, three
+512^2 instruments at inclinations 0/60/90 deg, 1e7 packets per wavelength,
+FP32 transport with FP64 table totals.  One step runs one contiguous block of
+packet ids of every wavelength (run_into: the blocks of consecutive steps add
+up to the whole job); the timed region holds exactly K steps with the scene
+already resident in HBM.
+
+Prints ONE JSON line with packets/s, the roofline of the transport kernel
+(algorithmic bytes from the kernel's own cell/pixel counters over its HIP-event
+duration, against 8 TB/s HBM) and the FP64 CPU oracle timed on the host cores
+on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon packets/s on 1 MI355X; image RMS err x time, learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per unit (FP32 production mode)
+B_PROP = 4 + 8      # density read + FP64 atomic payload per propagation cell
+B_LOCATE = 4        # density read per cell of the interaction search
+B_PEEL = 4          # density read per peel-off cell
+B_PIXEL = 4         # FP32 pixel atomic payload
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_04702_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.startswith("transport"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(st: dict) -> int:
+    return (B_PROP * st["prop_cells"] + B_LOCATE * st["locate_cells"] + B_PEEL * st["peel_cells"]
+            + B_PIXEL * st["peel_adds"])
+
+
+def make_scene(name: str):
+    from paper_1705_04702_amd import scenes
+    if name == "disk":
+        return scenes.disk(), ("exponential-disk galaxy: 256^3 Cartesian grid, 64 wavelengths "
+                               "0.1-1000 um, 3 x 512^2 instruments (i = 0/60/90 deg), "
+                               "1e7 packets per wavelength, FP32 transport, FP64 table totals")
+    if name == "sphere":
+        return scenes.sphere(), "uniform sphere tau=1: 32^3 grid, 1 wavelength, 64^2 instrument"
+    raise SystemExit(f"unknown workload {name}")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle, one wavelength per task, tasks spread over
+# processes (replicated scene, per-process tables summed -- the paper's task
+# parallel mode).
+# ---------------------------------------------------------------------------
+_SC = None
+
+
+def _oracle_task(args):
+    ell, n_per_lambda, count, seed = args
+    import numpy as np
+    import oracle
+    sc = _SC
+    sub = type(sc)(**{**sc.__dict__})
+    for f in ("lambdas", "kappa", "albedo", "hg_g", "lum"):
+        setattr(sub, f, np.ascontiguousarray(getattr(sc, f)[ell:ell + 1]))
+    t = time.perf_counter()
+    # a one-wavelength copy of the scene: same optics and cost, own streams
+    r = oracle.run(sub, n_per_lambda, seed=seed, first_id=0, count=count, model=0)
+    return r["stats"]["packets"], time.perf_counter() - t
+
+
+def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
+    global _SC
+    import oracle
+    oracle.lib()
+    _SC = scene
+    cores = min(16, os.cpu_count() or 1)
+    # calibrate on one task
+    t0 = time.perf_counter()
+    _oracle_task((scene.n_lambda // 2, n_per_lambda, 50, 0))
+    per_packet = (time.perf_counter() - t0) / 50.0
+    count = max(20, int(seconds_target * cores / max(per_packet, 1e-7) / scene.n_lambda))
+    tasks = [(ell, n_per_lambda, count, 0) for ell in range(scene.n_lambda)]
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_task, tasks, chunksize=1)
+    wall = time.perf_counter() - t
+    packets = sum(r[0] for r in res)
+    return {"value": packets / wall, "unit": "packets/s", "cores": cores, "kind": "oracle",
+            "sample": f"packet ids [0, {count}) of each of the {scene.n_lambda} wavelengths "
+                      f"({packets} packets, {wall:.1f} s wall), one wavelength per task on "
+                      f"{cores} processes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="disk")
+    ap.add_argument("--n-per-lambda", type=int, default=10_000_000)
+    ap.add_argument("--step-packets", type=int, default=500_000,
+                    help="packet ids per wavelength in one step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--threshold", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is documented, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1705_04702_amd import mcrt
+
+    torch.cuda.set_device(0)
+    scene, workload = make_scene(args.workload)
+    N = args.n_per_lambda
+    B = min(args.step_packets, N)
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, scene, mcrt.FP32, chunk=args.chunk or None,
+                   waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None)
+    res = sim.new_result()
+    nl = scene.n_lambda
+    print(f"[bench] workload={args.workload} n_lambda={nl} step={B} ids/lambda "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+
+    def step(k):
+        first = (k * B) % N
+        cnt = min(B, N - first)
+        sim.run_into(res, N, seed=0, first_id=first, count=cnt)
+        st = res.stats()
+        return cnt * nl, st
+
+    for w in range(args.warmup):
+        step(w)
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    res.zero()
+    torch.cuda.synchronize()
+    prev = res.stats()
+    kernel_ms, packets, bytes_alg = [], 0, 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        n, st = step(k)
+        packets += n
+        kernel_ms.append(st["kernel_ms"])
+        delta = {f: st[f] - prev[f] for f in mcrt.STAT_FIELDS}
+        bytes_alg += algorithmic_bytes(delta)
+        prev = st
+        print(f"[bench] step {k}: {n} packets, kernel {st['kernel_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    e = res.energy()
+    balance = abs(e[0] - e[1] - e[2] - e[3]) / e[0]
+    st = res.stats()
+
+    avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    achieved = bytes_alg / args.steps / avg_kernel_s / 1e9
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", f"transport_{args.workload}_traffic.json")
+    if os.path.exists(prof):
+        meta = json.load(open(prof))
+        if meta.get("kernel_hash") == kernel_sources_hash():
+            traffic = meta["hbm_bytes_per_packet"] * packets / args.steps
+    out = {
+        "metric": METRIC,
+        "value": packets / T,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "n_per_lambda": N, "packets_per_step": B * nl,
+                   "grid": list(scene.n), "n_lambda": nl,
+                   "instruments": [list(i.npix) for i in scene.instruments]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "energy_balance": balance,
+        "counters_per_packet": {f: st[f] / max(st["packets"], 1) for f in
+                                ("events", "prop_cells", "locate_cells", "peel_cells", "peel_adds")},
+        "kernel_ms_avg": avg_kernel_s * 1e3,
+    }
+    res.close()
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

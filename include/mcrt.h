@@ -1,0 +1,194 @@
+/*
+ * mcrt.h -- C-ABI of the MI355X photon-packet transport library.
+ *
+ * The library runs the stellar emission phase of a Monte Carlo dust
+ * radiative-transfer simulation as described in the hybrid-parallel SKIRT
+ * paper (Verstocken et al. 2017), Section 3.2 "Stellar emission phase": for
+ * each wavelength a fixed number of photon packets is launched from the
+ * primary source, propagated through the dust grid while it loses
+ * luminosity continuously to absorption (written to the per-cell,
+ * per-wavelength absorbed-luminosity table), forced to interact, scattered,
+ * and peeled off towards every instrument at emission and at every
+ * scattering event, until only a negligible part of its launch luminosity
+ * remains.  The table is the "absorbed stellar luminosity" table of Fig. 2
+ * and Section 5.2 (ParallelTable, element (i, j) = cell i, wavelength j);
+ * additions to it are lock-free (Section 5.2 "Lockfree additions"), here as
+ * hardware FP64 atomic adds.  The client needs only a handful of calls
+ * (Section 5.1.1, "the client").
+ *
+ * Conventions
+ *  - Every function returns MCRT_OK (0) or a negative MCRT_E* code; the
+ *    thread-local message of the last failure is mcrt_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Handles are opaque, created and destroyed only by the library.  A
+ *    handle must outlive every handle created from it (context > grid >
+ *    medium > sim > result; source and instrument > sim).
+ *  - Input arrays are host memory, copied at create time; the caller keeps
+ *    ownership.
+ *  - Result readers copy into a caller buffer that may be host memory or
+ *    device memory on the context's device; `count` (elements) is checked and
+ *    MCRT_EINVAL is returned if it is smaller than required.
+ *  - All device work of a call runs on the context's stream; every call
+ *    returns after that work has completed.
+ *  - One run per simulation at a time: a second concurrent run on the same
+ *    sim returns MCRT_EBUSY (the single-owner rule of the paper's
+ *    ProcessManager, Section 5.1).
+ *  - Units are arbitrary but consistent: lengths (grid box, distances, field
+ *    of view) in one unit, kappa is extinction per unit density per unit
+ *    length, luminosities per wavelength bin.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRT_OK 0
+#define MCRT_EINVAL (-1)  /* invalid handle, argument or size */
+#define MCRT_ENOMEM (-2)  /* device or host allocation failed */
+#define MCRT_EDEVICE (-3) /* HIP runtime error */
+#define MCRT_EBUSY (-4)   /* the simulation is already running */
+#define MCRT_ELIMIT (-5)  /* packets hit the event cap; results are valid, see stats.capped */
+
+#define MCRT_FP32 0           /* FP32 transport, FP64 table totals and energy sums */
+#define MCRT_FP64_VALIDATE 1  /* FP64 throughout, no contraction */
+
+#define MCRT_MAX_INSTRUMENTS 8
+
+typedef struct mcrt_context mcrt_context;
+typedef struct mcrt_grid mcrt_grid;
+typedef struct mcrt_medium mcrt_medium;
+typedef struct mcrt_source mcrt_source;
+typedef struct mcrt_instrument mcrt_instrument;
+typedef struct mcrt_sim mcrt_sim;
+typedef struct mcrt_result mcrt_result;
+
+typedef struct {
+    int32_t precision;     /* MCRT_FP32 or MCRT_FP64_VALIDATE */
+    double w_min;          /* a packet ends once its scattered luminosity drops below
+                              w_min times its launch luminosity ("negligible part",
+                              Section 3.2); default 1e-6 */
+    int64_t event_cap;     /* maximum scattering events per packet; default 10000 */
+    double tau_peel_max;   /* peel-offs whose optical depth to the observer reaches this
+                              contribute nothing; default 40 */
+    int32_t chunk;         /* packets per work-queue grab; 0 = default */
+    int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = default */
+    int32_t threshold;     /* lanes that must finish a march before events run; 0 = default */
+    int32_t top_level;     /* octree top-table level; -1 = default */
+} mcrt_options;
+
+typedef struct {
+    uint64_t packets;      /* packets launched */
+    uint64_t events;       /* forced interactions followed by a scattering */
+    uint64_t prop_cells;   /* cells crossed by propagation marches (with deposits) */
+    uint64_t locate_cells; /* cells crossed while locating interaction points */
+    uint64_t peel_cells;   /* cells crossed by peel-off marches */
+    uint64_t peel_adds;    /* pixel additions */
+    uint64_t peel_dropped; /* peel-offs cut by tau_peel_max */
+    uint64_t capped;       /* packets that hit the event cap */
+    uint64_t guard;        /* octree marches stopped by the step guard (0 for valid trees) */
+    double kernel_ms;      /* transport kernel time of the last run into this result */
+} mcrt_stats;
+
+/* Fills *opt with the defaults listed above. */
+void mcrt_options_default(mcrt_options *opt);
+
+/* Binds a device (HIP ordinal) and a stream (a hipStream_t such as torch's
+ * current_stream().cuda_stream, or NULL for the default stream). */
+int mcrt_context_create(int device, void *hip_stream_or_null, mcrt_context **out);
+void mcrt_context_destroy(mcrt_context *ctx);
+
+/* Dust grid (Section 3.2, setup phase).  Cartesian: box = {xmin, ymin, zmin,
+ * xmax, ymax, zmax}, n cells per axis; cell index m = ix + nx (iy + ny iz),
+ * planes at xmin + j (xmax - xmin) / nx. */
+int mcrt_grid_create_cartesian(mcrt_context *ctx, const double box[6], const int32_t n[3],
+                               mcrt_grid **out);
+/* Octree: first_child[node] is the index of the node's first child or -1 for
+ * a leaf; the 8 children are contiguous in the order c = bx + 2 by + 4 bz;
+ * node 0 is the root (the whole box); leaves are numbered in depth-first
+ * order; maximum depth 15, fewer than 2^27 nodes. */
+int mcrt_grid_create_octree(mcrt_context *ctx, const double box[6], int64_t n_nodes,
+                            const int32_t *first_child, mcrt_grid **out);
+void mcrt_grid_destroy(mcrt_grid *grid);
+
+/* Dust medium: density per cell (grid order), and per wavelength the
+ * extinction coefficient kappa (per unit density and length), the albedo and
+ * the Henyey-Greenstein asymmetry parameter g.  lambda_um may be NULL. */
+int mcrt_medium_create(mcrt_grid *grid, const float *density, int32_t n_lambda,
+                       const double *lambda_um, const double *kappa, const double *albedo,
+                       const double *g, mcrt_medium **out);
+void mcrt_medium_destroy(mcrt_medium *medium);
+
+/* Primary sources with a-priori known emission (Section 3.2), luminosity L
+ * per wavelength bin.  Point source at pos: aniso = 0 isotropic, 1 angular
+ * distribution 2|cos theta| about the z axis.  Exponential disk: surface
+ * density exp(-R/hR), vertical sech^2(z/zs), centred at the origin in the
+ * z = 0 plane. */
+int mcrt_source_create_point(mcrt_context *ctx, const double pos[3], int32_t aniso,
+                             int32_t n_lambda, const double *L, mcrt_source **out);
+int mcrt_source_create_expdisk(mcrt_context *ctx, double hR, double zs, int32_t n_lambda,
+                               const double *L, mcrt_source **out);
+void mcrt_source_destroy(mcrt_source *src);
+
+/* Distant observer with parallel projection (the instrument table of
+ * Section 3.2): viewing direction (sin i cos a, sin i sin a, cos i), sky
+ * axes e_x = (-sin a, cos a, 0) and e_y = (-cos i cos a, -cos i sin a, sin i),
+ * field of view fov[2] centred on the origin, npix[2] = {nx, ny} pixels.
+ * Images hold flux L phase exp(-tau) / (4 pi distance^2) per pixel. */
+int mcrt_instrument_create(mcrt_context *ctx, double incl_deg, double azim_deg, double distance,
+                           const double fov[2], const int32_t npix[2], mcrt_instrument **out);
+void mcrt_instrument_destroy(mcrt_instrument *ins);
+
+/* Assembles a simulation and uploads the scene to the device.  opt may be
+ * NULL for defaults.  The medium's and source's n_lambda must agree. */
+int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
+                    mcrt_instrument *const *ins, int32_t n_ins, const mcrt_options *opt,
+                    mcrt_sim **out);
+void mcrt_sim_destroy(mcrt_sim *sim);
+
+/* A zeroed result (table, images, energy sums, stats) for the sim. */
+int mcrt_result_create(mcrt_sim *sim, mcrt_result **out);
+int mcrt_result_zero(mcrt_result *res);
+
+/* Runs packet ids [first_id, first_id + count) of every wavelength, each
+ * packet carrying L / n_per_lambda, and ADDS their contributions to res.
+ * Because absorbed luminosities add linearly (Section 5.2) and every packet
+ * has its own counter-based random stream, running disjoint id ranges into
+ * one result equals one run over their union (resume, sharding).  Returns
+ * MCRT_ELIMIT (with valid results) if any packet hit the event cap. */
+int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
+                  uint64_t seed, mcrt_result *res);
+/* Convenience: new result + run of all n_per_lambda packets per wavelength. */
+int mcrt_run(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t seed, mcrt_result **out);
+/* Convenience: new result + run of an id range. */
+int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
+                   uint64_t seed, mcrt_result **out);
+
+/* Absorbed luminosity table, out[i * n_lambda + j] for cell i and
+ * wavelength j (Section 5.2, ParallelTable element (i, j)); count >=
+ * n_cells * n_lambda. */
+int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count);
+/* Image of instrument ins, layout [lambda][y][x], flux units; count >=
+ * n_lambda * ny * nx. */
+int mcrt_result_image(const mcrt_result *res, int32_t ins, double *out, size_t count);
+/* Energy sums (FP64): emitted = absorbed + escaped + truncated. */
+int mcrt_result_energy(const mcrt_result *res, double *emitted, double *absorbed,
+                       double *escaped, double *truncated);
+int mcrt_result_stats(const mcrt_result *res, mcrt_stats *stats);
+void mcrt_result_destroy(mcrt_result *res);
+
+/* Sizes of a simulation, for sizing result buffers. */
+int mcrt_sim_info(const mcrt_sim *sim, int64_t *n_cells, int32_t *n_lambda, int32_t *n_ins);
+
+/* Thread-local message describing the last failure of this thread. */
+const char *mcrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

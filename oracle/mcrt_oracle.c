@@ -96,6 +96,153 @@ float or_uniform32(uint64_t seed, uint32_t packet, uint32_t lambda, uint32_t mod
     return ((float)(hi >> 9) + 0.5f) * 0x1p-23f;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Elementary functions with an explicitly specified operation sequence, so  */
+/* that FP64 results do not depend on the platform's math library:           */
+/* Cody & Waite additive argument reduction (W. J. Cody and W. Waite,        */
+/* "Software Manual for the Elementary Functions", 1980) followed by         */
+/* truncated Taylor series in Horner form; the logarithm through the series  */
+/* of 2 atanh(s), s = (m - 1)/(m + 1); log1p through the correction of       */
+/* Goldberg, "What every computer scientist should know about floating-point */
+/* arithmetic" (1991), Theorem 4.  Each is within a few ulp of the exact     */
+/* value (pinned against the C library in the tests).                         */
+/* ------------------------------------------------------------------------ */
+
+static const double LN2_HI = 0x1.62e42fee00000p-1;  /* ln 2 to 32 bits */
+static const double LN2_LO = 0x1.a39ef35793c76p-33; /* ln 2 - LN2_HI */
+static const double INV_LN2 = 0x1.71547652b82fep+0;
+static const double SQRT2 = 0x1.6a09e667f3bcdp+0;
+static const double PIO2_1 = 0x1.921fb54400000p+0;  /* pi/2 to 33 bits */
+static const double PIO2_2 = 0x1.0b4611a600000p-34; /* next 33 bits */
+static const double PIO2_3 = 0x1.3198a2e037073p-69; /* remainder */
+static const double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+
+/* 1/j!, j = 0 .. 22 */
+static const double INV_FACT[23] = {
+    1.0, 1.0, 0x1.0000000000000p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5,
+    0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16,
+    0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29,
+    0x1.6124613a86d09p-33, 0x1.93974a8c07c9dp-37, 0x1.ae7f3e733b81fp-41, 0x1.ae7f3e733b81fp-45,
+    0x1.952c77030ad4ap-49, 0x1.6827863b97d97p-53, 0x1.2f49b46814157p-57, 0x1.e542ba4020225p-62,
+    0x1.71b8ef6dcf572p-66, 0x1.0ce396db7f853p-70};
+
+/* 1/(2j+1), j = 0 .. 11 */
+static const double INV_ODD[12] = {
+    1.0, 0x1.5555555555555p-2, 0x1.999999999999ap-3, 0x1.2492492492492p-3, 0x1.c71c71c71c71cp-4,
+    0x1.745d1745d1746p-4, 0x1.3b13b13b13b14p-4, 0x1.1111111111111p-4, 0x1.e1e1e1e1e1e1ep-5,
+    0x1.af286bca1af28p-5, 0x1.8618618618618p-5, 0x1.642c8590b2164p-5};
+
+static double pow2i(int j) /* 2^j for -1022 <= j <= 1023 */
+{
+    uint64_t b = (uint64_t)(j + 1023) << 52;
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+/* p * 2^k with at most one rounding (into the subnormal range) */
+static double scale2(double p, int k)
+{
+    if (k > 1023) return p * pow2i(1023) * pow2i(k - 1023);
+    if (k < -1022) return p * pow2i(-1022) * pow2i(k + 1022);
+    return p * pow2i(k);
+}
+
+double or_exp(double x)
+{
+    if (x != x) return x;
+    if (x > 709.782712893384) return INFINITY;
+    if (x < -745.2) return 0.0;
+    double kd = floor(x * INV_LN2 + 0.5);
+    double r = (x - kd * LN2_HI) - kd * LN2_LO;
+    /* e^r = sum_{j=0}^{13} r^j / j!,  |r| <= 0.3466 */
+    double p = INV_FACT[13];
+    for (int j = 12; j >= 0; --j) p = p * r + INV_FACT[j];
+    return scale2(p, (int)kd);
+}
+
+double or_expm1(double x)
+{
+    if (x != x) return x;
+    if (fabs(x) < 1.0) {
+        /* x * sum_{j=0}^{21} x^j / (j+1)!,  |x| < 1 */
+        double p = INV_FACT[22];
+        for (int j = 21; j >= 1; --j) p = p * x + INV_FACT[j];
+        return x * p;
+    }
+    return or_exp(x) - 1.0;
+}
+
+double or_log(double x)
+{
+    if (x != x || x < 0.0) return NAN;
+    if (x == 0.0) return -INFINITY;
+    if (x == INFINITY) return x;
+    int e = 0;
+    if (x < 0x1p-1022) {
+        x = x * 0x1p54;
+        e = -54;
+    }
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    e += (int)((b >> 52) & 0x7ff) - 1023;
+    b = (b & 0x000fffffffffffffull) | (0x3ffull << 52);
+    double m;
+    memcpy(&m, &b, sizeof m); /* m in [1, 2) */
+    if (m > SQRT2) {
+        m = m * 0.5;
+        e += 1;
+    }
+    double f = m - 1.0;
+    double s = f / (2.0 + f);
+    double s2 = s * s;
+    /* log m = 2 s sum_{j=0}^{11} s^(2j) / (2j+1) */
+    double q = INV_ODD[11];
+    for (int j = 10; j >= 0; --j) q = q * s2 + INV_ODD[j];
+    double lm = 2.0 * s * q;
+    double de = (double)e;
+    return de * LN2_HI + (de * LN2_LO + lm);
+}
+
+double or_log1p(double x)
+{
+    if (x != x) return x;
+    if (x == -1.0) return -INFINITY;
+    if (x < -1.0) return NAN;
+    double u = 1.0 + x;
+    if (u == 1.0) return x;
+    return or_log(u) * (x / (u - 1.0));
+}
+
+/* atanh |x| = log1p(2|x| / (1 - |x|)) / 2, odd symmetry */
+double or_atanh(double x)
+{
+    double ax = fabs(x);
+    double h = 0.5 * or_log1p((2.0 * ax) / (1.0 - ax));
+    return x < 0.0 ? -h : h;
+}
+
+void or_sincos(double x, double *sn, double *cs)
+{
+    double q = floor(x * TWO_OVER_PI + 0.5);
+    double r = ((x - q * PIO2_1) - q * PIO2_2) - q * PIO2_3;
+    double r2 = r * r;
+    /* sin r = r sum_{j=0}^{9} (-1)^j r^(2j) / (2j+1)!,
+     * cos r = sum_{j=0}^{10} (-1)^j r^(2j) / (2j)!,  |r| <= pi/4 */
+    double ps = -INV_FACT[19];
+    for (int j = 8; j >= 0; --j) ps = (j % 2 ? -INV_FACT[2 * j + 1] : INV_FACT[2 * j + 1]) + r2 * ps;
+    double pc = INV_FACT[20];
+    for (int j = 9; j >= 0; --j) pc = (j % 2 ? -INV_FACT[2 * j] : INV_FACT[2 * j]) + r2 * pc;
+    double sr = r * ps, cr = pc;
+    long long n = (long long)q;
+    int quad = (int)(((n % 4) + 4) % 4);
+    if (quad == 0) { *sn = sr; *cs = cr; }
+    else if (quad == 1) { *sn = cr; *cs = -sr; }
+    else if (quad == 2) { *sn = -sr; *cs = -cr; }
+    else { *sn = -cr; *cs = sr; }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: the dust grid and the ray march.                               */
 /* ------------------------------------------------------------------------ */
@@ -428,7 +575,8 @@ static void rotate_about_pole(double a, double b, double c, double mu, double st
 void or_rotate(const double k[3], double mu, double phi, double out[3])
 {
     double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double cp = cos(phi), sp = sin(phi);
+    double sp, cp;
+    or_sincos(phi, &sp, &cp);
     double x, y, z;
     if (fabs(k[2]) < 0.99999) {
         rotate_about_pole(k[0], k[1], k[2], mu, st, cp, sp, &x, &y, &z);
@@ -531,7 +679,7 @@ static int peel(runctx *c, int ell, const double r[3], double lum, double phase,
     double px = floor((x + 0.5 * in->fovx) / (in->fovx / (double)in->nx));
     double py = floor((y + 0.5 * in->fovy) / (in->fovy / (double)in->ny));
     if (px < 0.0 || px >= (double)in->nx || py < 0.0 || py >= (double)in->ny) return 0;
-    double flux = lum * phase * exp(-tau) * in->inv4pid2;
+    double flux = lum * phase * or_exp(-tau) * in->inv4pid2;
     int64_t idx = in->offset + ((int64_t)ell * in->ny + (int64_t)py) * in->nx + (int64_t)px;
     c->out->images[idx] += flux;
     moment_add(&c->mi, idx, flux);
@@ -554,11 +702,13 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
     /* launch */
     double r[3], k[3];
     if (s->source_type == OR_SRC_EXPDISK) {
-        double R = -s->disk_hR * log(U(0) * U(1));
+        double R = -s->disk_hR * or_log(U(0) * U(1));
         double phi = 2.0 * OR_PI * U(2);
-        double z = s->disk_zs * atanh(2.0 * U(3) - 1.0);
-        r[0] = R * cos(phi);
-        r[1] = R * sin(phi);
+        double z = s->disk_zs * or_atanh(2.0 * U(3) - 1.0);
+        double sphi, cphi;
+        or_sincos(phi, &sphi, &cphi);
+        r[0] = R * cphi;
+        r[1] = R * sphi;
         r[2] = z;
     } else {
         r[0] = s->src_pos[0];
@@ -574,8 +724,10 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
     }
     double phi = 2.0 * OR_PI * U(6);
     double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-    k[0] = st * cos(phi);
-    k[1] = st * sin(phi);
+    double sphi, cphi;
+    or_sincos(phi, &sphi, &cphi);
+    k[0] = st * cphi;
+    k[1] = st * sphi;
     k[2] = mu;
     o->energy[0] += L0;
     o->stats.packets++;
@@ -598,7 +750,7 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
             double ds = c->sl.tend[n] - prev;
             prev = c->sl.tend[n];
             double dtau = kappa * (double)s->density[m] * ds;
-            double x = -expm1(-dtau);
+            double x = -or_expm1(-dtau);
             double A = wabs * E * x;
             int64_t ti = m * s->n_lambda + ell;
             o->table[ti] += A;
@@ -617,7 +769,7 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
             break;
         }
         /* forced interaction point */
-        double tau_int = -log1p(-U(8 * e + 0) * (1.0 - Epath));
+        double tau_int = -or_log1p(-U(8 * e + 0) * (1.0 - Epath));
         int64_t nstar = -1, nlast = -1;
         double taucum = 0.0, taustar_prev = 0.0, taulast_prev = 0.0;
         prev = c->sl.t0;

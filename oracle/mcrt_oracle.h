@@ -93,6 +93,14 @@ float or_uniform32(uint64_t seed, uint32_t packet, uint32_t lambda, uint32_t mod
 int64_t or_march(const or_scene *scene, const double r[3], const double k[3],
                  int64_t *cells, double *lengths, int64_t max_seg);
 
+/* Elementary functions with a platform-independent operation sequence. */
+double or_exp(double x);
+double or_expm1(double x);
+double or_log(double x);
+double or_log1p(double x);
+double or_atanh(double x);
+void or_sincos(double x, double *s, double *c);
+
 /* Henyey-Greenstein phase function and sampler. */
 double or_hg_phase(double g, double mu);
 double or_hg_sample(double g, double u);

@@ -1,0 +1,172 @@
+// lanesim.cpp -- serial host instantiation of the transport lane logic
+// (transport_core.h), packet after packet in (wavelength, id) order, with
+// plain additions in place of the device atomics.
+//
+// TEST HARNESS: it lets the CPU test suite check the kernel's per-lane code
+// (march, event processing, sampling, scene setup) without a GPU.  It is not
+// used by the library or its Python binding.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace mcrt {
+using std::atanh;
+using std::cos;
+using std::exp;
+using std::expm1;
+using std::fabs;
+using std::floor;
+using std::log;
+using std::log1p;
+using std::sin;
+using std::sqrt;
+} // namespace mcrt
+
+#define MCRT_HD inline
+#include "transport_core.h"
+#include "scene_setup.h"
+
+using namespace mcrt;
+
+namespace {
+struct HostSink {
+    void deposit(double *p, double v)
+    {
+        if (v != 0.0) *p += v;
+    }
+    void pixel(float *p, float v) { *p += v; }
+    void pixel(double *p, double v) { *p += v; }
+};
+} // namespace
+
+extern "C" {
+
+typedef struct {
+    int32_t grid_type;
+    double box[6];
+    int32_t n[3];
+    int64_t n_nodes;
+    const int32_t *first_child;
+    int64_t n_cells;
+    const float *density;
+    int32_t n_lambda;
+    const double *kappa, *albedo, *g, *L;
+    int32_t src_type;
+    double src_pos[3];
+    double hR, zs;
+    int32_t n_ins;
+    const double *ins_geom;   // [n_ins][5] incl, azim, distance, fov_x, fov_y
+    const int32_t *ins_npix;  // [n_ins][2]
+    double w_min;
+    int64_t event_cap;
+    double tau_peel_max;
+    int32_t precision;        // 0 FP32, 1 FP64
+    int32_t top_level;        // -1 default
+} ls_scene;
+
+typedef struct {
+    double *table;   // [n_cells][n_lambda]
+    double *images;  // concatenated [n_lambda][ny][nx] per instrument, flux
+    double *energy;  // [4]
+    uint64_t *stats; // [9]
+} ls_out;
+
+}
+
+template <typename Real>
+static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, uint64_t seed, ls_out *o)
+{
+    View<Real, Real> v{};
+    std::vector<int32_t> node, top;
+    int depth = 0;
+    if (s->grid_type == kOctree) {
+        std::string err;
+        depth = encode_octree(s->n_nodes, s->first_child, s->n_cells, node, err);
+        if (depth < 0) return -2;
+        v.top_level = s->top_level >= 0 ? (s->top_level < depth ? s->top_level : depth) : (depth < 7 ? depth : 7);
+        build_top_table(node, v.top_level, top);
+        for (int a = 0; a < 3; ++a) v.n[a] = 1 << depth;
+    } else {
+        for (int a = 0; a < 3; ++a) v.n[a] = s->n[a];
+    }
+    v.grid_type = s->grid_type;
+    v.depth = depth;
+    for (int a = 0; a < 3; ++a) {
+        v.lo[a] = (Real)s->box[a];
+        v.hi[a] = (Real)s->box[3 + a];
+        v.cs[a] = (Real)((s->box[3 + a] - s->box[a]) / (double)v.n[a]);
+    }
+    v.density = s->density;
+    v.node = node.data();
+    v.top = top.data();
+    v.n_cells = s->n_cells;
+    v.n_lambda = s->n_lambda;
+    std::vector<Optics<Real>> optics((size_t)s->n_lambda);
+    for (int l = 0; l < s->n_lambda; ++l)
+        optics[l] = Optics<Real>{(Real)s->kappa[l], (Real)s->albedo[l], (Real)s->g[l], (Real)(s->L[l] / (double)npl)};
+    v.optics = optics.data();
+    v.src_type = s->src_type;
+    for (int a = 0; a < 3; ++a) v.src_pos[a] = (Real)s->src_pos[a];
+    v.hR = (Real)s->hR;
+    v.zs = (Real)s->zs;
+    v.n_ins = s->n_ins;
+    std::vector<InsDesc<Real>> ins((size_t)(s->n_ins > 0 ? s->n_ins : 1));
+    std::vector<double> inv4pid2((size_t)(s->n_ins > 0 ? s->n_ins : 1));
+    long long off = 0;
+    for (int j = 0; j < s->n_ins; ++j) {
+        const double *gm = s->ins_geom + 5 * j;
+        HostInstrument h{gm[0], gm[1], gm[2], {gm[3], gm[4]}, {s->ins_npix[2 * j], s->ins_npix[2 * j + 1]}};
+        make_ins_desc<Real>(h, off, ins[j], inv4pid2[j]);
+        off += (long long)s->n_lambda * h.npix[0] * h.npix[1];
+    }
+    v.ins = ins.data();
+    std::vector<double> table((size_t)s->n_cells * s->n_lambda, 0.0);
+    std::vector<Real> images((size_t)(off > 0 ? off : 1), Real(0));
+    v.table = table.data();
+    v.images = images.data();
+    v.w_min = (Real)s->w_min;
+    v.event_cap = s->event_cap;
+    v.tau_peel_max = (Real)s->tau_peel_max;
+    v.octree_guard = 16 * 3 * (1 << depth) + 64;
+    v.key0 = (uint32_t)(seed & 0xffffffffu);
+    v.key1 = (uint32_t)(seed >> 32);
+    v.model = 0;
+
+    HostSink sink;
+    Tally ty{};
+    for (int l = 0; l < s->n_lambda; ++l) {
+        for (uint64_t i = first; i < first + count; ++i) {
+            Lane<Real> ln{};
+            launch(v, ln, ty, (uint32_t)l, (uint32_t)i);
+            settle(v, ln, ty, sink);
+            while (ln.mode != kDead) {
+                march_step(v, ln, ty, sink);
+                if (!ln.marching) settle(v, ln, ty, sink);
+            }
+        }
+    }
+    for (int64_t c = 0; c < s->n_cells; ++c)
+        for (int l = 0; l < s->n_lambda; ++l) o->table[c * s->n_lambda + l] = table[(size_t)l * s->n_cells + c];
+    for (int j = 0; j < s->n_ins; ++j) {
+        long long n = (long long)s->n_lambda * s->ins_npix[2 * j] * s->ins_npix[2 * j + 1];
+        for (long long q = 0; q < n; ++q) o->images[ins[j].offset + q] = (double)images[ins[j].offset + q] * inv4pid2[j];
+    }
+    o->energy[0] = ty.emitted;
+    o->energy[1] = ty.absorbed;
+    o->energy[2] = ty.escaped;
+    o->energy[3] = ty.truncated;
+    uint64_t st[9] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells, ty.peel_cells,
+                      ty.peel_adds, ty.peel_dropped, ty.capped, ty.guard};
+    std::memcpy(o->stats, st, sizeof(st));
+    return 0;
+}
+
+extern "C" int ls_run(const ls_scene *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                      ls_out *out)
+{
+    if (!s || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
+    if (s->precision == 1) return run<double>(s, n_per_lambda, first_id, count, seed, out);
+    return run<float>(s, n_per_lambda, first_id, count, seed, out);
+}

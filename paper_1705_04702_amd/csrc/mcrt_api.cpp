@@ -1,0 +1,725 @@
+// mcrt_api.cpp -- implementation of the C-ABI declared in include/mcrt.h:
+// handle management, argument validation, scene upload, run orchestration
+// and result readback.  All arithmetic of the photon life cycle runs in the
+// HIP kernels; this file only prepares constants and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcrt.h"
+
+#define MCRT_HD inline
+#include "transport_core.h"
+#include "internal.h"
+#include "scene_setup.h"
+
+using namespace mcrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return fail(MCRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool debug_fail_alloc()
+{
+    const char *s = std::getenv("MCRT_DEBUG_FAIL_ALLOC");
+    return s && s[0] == '1';
+}
+
+int dev_alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (debug_fail_alloc()) return fail(MCRT_ENOMEM, "device allocation refused (MCRT_DEBUG_FAIL_ALLOC=1)");
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(MCRT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    return MCRT_OK;
+}
+
+void dev_free(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+bool finite_box(const double b[6])
+{
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(b[a]) || !std::isfinite(b[3 + a]) || !(b[3 + a] > b[a])) return false;
+    return true;
+}
+
+} // namespace
+
+struct mcrt_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+};
+
+struct mcrt_grid {
+    mcrt_context *ctx = nullptr;
+    int type = kCartesian;
+    double box[6] = {};
+    int n[3] = {0, 0, 0};
+    int depth = 0;
+    int64_t n_cells = 0;
+    std::vector<int32_t> first_child;
+};
+
+struct mcrt_medium {
+    mcrt_grid *grid = nullptr;
+    std::vector<float> density;
+    int n_lambda = 0;
+    std::vector<double> kappa, albedo, g;
+};
+
+struct mcrt_source {
+    mcrt_context *ctx = nullptr;
+    int type = kPointIso;
+    double pos[3] = {0, 0, 0};
+    double hR = 0, zs = 0;
+    std::vector<double> L;
+};
+
+struct mcrt_instrument {
+    mcrt_context *ctx = nullptr;
+    HostInstrument h{};
+};
+
+struct mcrt_sim {
+    mcrt_context *ctx = nullptr;
+    mcrt_medium *medium = nullptr;
+    mcrt_source *source = nullptr;
+    int n_ins = 0;
+    HostInstrument ins[kMaxIns];
+    double inv4pid2[kMaxIns];
+    long long ins_offset[kMaxIns];
+    long long image_elems = 0;
+    mcrt_options opt{};
+    int depth = 0, top_level = 0;
+    // device copies of the scene
+    float *d_density = nullptr;
+    int *d_node = nullptr;
+    int *d_top = nullptr;
+    void *d_optics = nullptr; // Optics<Real>[n_lambda], rewritten per run
+    void *d_ins = nullptr;    // InsDesc<Real>[n_ins]
+    std::atomic<int> busy{0};
+};
+
+struct mcrt_result {
+    mcrt_sim *sim = nullptr;
+    double *d_table = nullptr;    // [n_lambda][n_cells]
+    void *d_images = nullptr;     // float or double, [ins][lambda][y][x]
+    double *d_energy = nullptr;   // [4]
+    unsigned long long *d_stats = nullptr;   // [kNumStats]
+    unsigned long long *d_counter = nullptr; // queue position
+    double kernel_ms = 0.0;
+};
+
+// Definitions of the functions declared extern "C" in mcrt.h (they keep C
+// linkage from that declaration).
+
+const char *mcrt_last_error(void) { return g_err.c_str(); }
+
+void mcrt_options_default(mcrt_options *opt)
+{
+    if (!opt) return;
+    opt->precision = MCRT_FP32;
+    opt->w_min = 1e-6;
+    opt->event_cap = 10000;
+    opt->tau_peel_max = 40.0;
+    opt->chunk = 0;
+    opt->waves_per_cu = 0;
+    opt->threshold = 0;
+    opt->top_level = -1;
+}
+
+int mcrt_context_create(int device, void *stream, mcrt_context **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "context_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(MCRT_EINVAL, "context_create: no such device");
+    HIP_TRY(hipSetDevice(device));
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+    auto *c = new mcrt_context;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->n_cu = ncu > 0 ? ncu : 1;
+    *out = c;
+    return MCRT_OK;
+}
+
+void mcrt_context_destroy(mcrt_context *ctx) { delete ctx; }
+
+int mcrt_grid_create_cartesian(mcrt_context *ctx, const double box[6], const int32_t n[3], mcrt_grid **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "grid_create_cartesian: out is NULL");
+    *out = nullptr;
+    if (!ctx || !box || !n) return fail(MCRT_EINVAL, "grid_create_cartesian: NULL argument");
+    if (!finite_box(box)) return fail(MCRT_EINVAL, "grid_create_cartesian: box must have min < max, finite");
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] <= 0) return fail(MCRT_EINVAL, "grid_create_cartesian: cell counts must be positive");
+        cells *= n[a];
+    }
+    if (cells >= (int64_t(1) << 31)) return fail(MCRT_EINVAL, "grid_create_cartesian: more than 2^31-1 cells");
+    auto *g = new mcrt_grid;
+    g->ctx = ctx;
+    g->type = kCartesian;
+    std::memcpy(g->box, box, sizeof(g->box));
+    for (int a = 0; a < 3; ++a) g->n[a] = n[a];
+    g->n_cells = cells;
+    *out = g;
+    return MCRT_OK;
+}
+
+int mcrt_grid_create_octree(mcrt_context *ctx, const double box[6], int64_t n_nodes, const int32_t *first_child,
+                            mcrt_grid **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "grid_create_octree: out is NULL");
+    *out = nullptr;
+    if (!ctx || !box || !first_child) return fail(MCRT_EINVAL, "grid_create_octree: NULL argument");
+    if (!finite_box(box)) return fail(MCRT_EINVAL, "grid_create_octree: box must have min < max, finite");
+    if (n_nodes <= 0 || n_nodes >= (int64_t(1) << 27)) return fail(MCRT_EINVAL, "grid_create_octree: node count out of range");
+    int64_t leaves = 0;
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (first_child[i] < 0) leaves++;
+    std::vector<int32_t> node;
+    std::string err;
+    int depth = encode_octree(n_nodes, first_child, leaves, node, err);
+    if (depth < 0) return fail(MCRT_EINVAL, "grid_create_octree: " + err);
+    auto *g = new mcrt_grid;
+    g->ctx = ctx;
+    g->type = kOctree;
+    std::memcpy(g->box, box, sizeof(g->box));
+    g->depth = depth;
+    for (int a = 0; a < 3; ++a) g->n[a] = 1 << depth;
+    g->n_cells = leaves;
+    g->first_child.assign(first_child, first_child + n_nodes);
+    *out = g;
+    return MCRT_OK;
+}
+
+void mcrt_grid_destroy(mcrt_grid *grid) { delete grid; }
+
+int mcrt_medium_create(mcrt_grid *grid, const float *density, int32_t n_lambda, const double *lambda_um,
+                       const double *kappa, const double *albedo, const double *g, mcrt_medium **out)
+{
+    (void)lambda_um;
+    if (!out) return fail(MCRT_EINVAL, "medium_create: out is NULL");
+    *out = nullptr;
+    if (!grid || !density || !kappa || !albedo || !g) return fail(MCRT_EINVAL, "medium_create: NULL argument");
+    if (n_lambda <= 0 || n_lambda > (1 << 20)) return fail(MCRT_EINVAL, "medium_create: n_lambda out of range");
+    for (int64_t i = 0; i < grid->n_cells; ++i)
+        if (!(density[i] >= 0.0f) || !std::isfinite(density[i]))
+            return fail(MCRT_EINVAL, "medium_create: densities must be finite and non-negative");
+    for (int l = 0; l < n_lambda; ++l) {
+        if (!(kappa[l] >= 0.0) || !std::isfinite(kappa[l])) return fail(MCRT_EINVAL, "medium_create: kappa must be finite, >= 0");
+        if (!(albedo[l] >= 0.0 && albedo[l] <= 1.0)) return fail(MCRT_EINVAL, "medium_create: albedo must lie in [0, 1]");
+        if (!(g[l] > -1.0 && g[l] < 1.0)) return fail(MCRT_EINVAL, "medium_create: g must lie in (-1, 1)");
+    }
+    auto *m = new mcrt_medium;
+    m->grid = grid;
+    m->density.assign(density, density + grid->n_cells);
+    m->n_lambda = n_lambda;
+    m->kappa.assign(kappa, kappa + n_lambda);
+    m->albedo.assign(albedo, albedo + n_lambda);
+    m->g.assign(g, g + n_lambda);
+    *out = m;
+    return MCRT_OK;
+}
+
+void mcrt_medium_destroy(mcrt_medium *medium) { delete medium; }
+
+static int check_lum(int32_t n_lambda, const double *L)
+{
+    if (n_lambda <= 0 || !L) return fail(MCRT_EINVAL, "source: n_lambda must be positive and L non-NULL");
+    for (int l = 0; l < n_lambda; ++l)
+        if (!(L[l] >= 0.0) || !std::isfinite(L[l])) return fail(MCRT_EINVAL, "source: luminosities must be finite, >= 0");
+    return MCRT_OK;
+}
+
+int mcrt_source_create_point(mcrt_context *ctx, const double pos[3], int32_t aniso, int32_t n_lambda, const double *L,
+                             mcrt_source **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "source_create_point: out is NULL");
+    *out = nullptr;
+    if (!ctx || !pos) return fail(MCRT_EINVAL, "source_create_point: NULL argument");
+    if (aniso != 0 && aniso != 1) return fail(MCRT_EINVAL, "source_create_point: aniso must be 0 or 1");
+    int rc = check_lum(n_lambda, L);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(pos[a])) return fail(MCRT_EINVAL, "source_create_point: position must be finite");
+    auto *s = new mcrt_source;
+    s->ctx = ctx;
+    s->type = aniso ? kPointAniso : kPointIso;
+    std::memcpy(s->pos, pos, sizeof(s->pos));
+    s->L.assign(L, L + n_lambda);
+    *out = s;
+    return MCRT_OK;
+}
+
+int mcrt_source_create_expdisk(mcrt_context *ctx, double hR, double zs, int32_t n_lambda, const double *L,
+                               mcrt_source **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "source_create_expdisk: out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(MCRT_EINVAL, "source_create_expdisk: NULL context");
+    if (!(hR > 0.0) || !(zs > 0.0) || !std::isfinite(hR) || !std::isfinite(zs))
+        return fail(MCRT_EINVAL, "source_create_expdisk: scales must be positive");
+    int rc = check_lum(n_lambda, L);
+    if (rc) return rc;
+    auto *s = new mcrt_source;
+    s->ctx = ctx;
+    s->type = kExpDisk;
+    s->hR = hR;
+    s->zs = zs;
+    s->L.assign(L, L + n_lambda);
+    *out = s;
+    return MCRT_OK;
+}
+
+void mcrt_source_destroy(mcrt_source *src) { delete src; }
+
+int mcrt_instrument_create(mcrt_context *ctx, double incl_deg, double azim_deg, double distance, const double fov[2],
+                           const int32_t npix[2], mcrt_instrument **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "instrument_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !fov || !npix) return fail(MCRT_EINVAL, "instrument_create: NULL argument");
+    if (!(distance > 0.0) || !std::isfinite(distance)) return fail(MCRT_EINVAL, "instrument_create: distance must be positive");
+    if (!std::isfinite(incl_deg) || !std::isfinite(azim_deg)) return fail(MCRT_EINVAL, "instrument_create: angles must be finite");
+    for (int a = 0; a < 2; ++a) {
+        if (!(fov[a] > 0.0) || !std::isfinite(fov[a])) return fail(MCRT_EINVAL, "instrument_create: field of view must be positive");
+        if (npix[a] <= 0 || npix[a] > 65536) return fail(MCRT_EINVAL, "instrument_create: pixel counts must be in 1 .. 65536");
+    }
+    auto *i = new mcrt_instrument;
+    i->ctx = ctx;
+    i->h = HostInstrument{incl_deg, azim_deg, distance, {fov[0], fov[1]}, {npix[0], npix[1]}};
+    *out = i;
+    return MCRT_OK;
+}
+
+void mcrt_instrument_destroy(mcrt_instrument *ins) { delete ins; }
+
+static void sim_free_device(mcrt_sim *s)
+{
+    dev_free(s->d_density);
+    dev_free(s->d_node);
+    dev_free(s->d_top);
+    dev_free(s->d_optics);
+    dev_free(s->d_ins);
+    s->d_density = nullptr;
+    s->d_node = nullptr;
+    s->d_top = nullptr;
+    s->d_optics = nullptr;
+    s->d_ins = nullptr;
+}
+
+void mcrt_sim_destroy(mcrt_sim *sim)
+{
+    if (!sim) return;
+    (void)hipSetDevice(sim->ctx->device);
+    sim_free_device(sim);
+    delete sim;
+}
+
+template <typename Real> static int upload_instruments(mcrt_sim *s)
+{
+    std::vector<InsDesc<Real>> d((size_t)std::max(s->n_ins, 1));
+    for (int j = 0; j < s->n_ins; ++j) make_ins_desc<Real>(s->ins[j], s->ins_offset[j], d[j], s->inv4pid2[j]);
+    int rc = dev_alloc(&s->d_ins, d.size() * sizeof(InsDesc<Real>));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(s->d_ins, d.data(), d.size() * sizeof(InsDesc<Real>), hipMemcpyHostToDevice));
+    rc = dev_alloc(&s->d_optics, (size_t)s->medium->n_lambda * sizeof(Optics<Real>));
+    return rc;
+}
+
+int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source, mcrt_instrument *const *ins,
+                    int32_t n_ins, const mcrt_options *opt, mcrt_sim **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "sim_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !medium || !source) return fail(MCRT_EINVAL, "sim_create: NULL argument");
+    if (n_ins < 0 || n_ins > kMaxIns || (n_ins > 0 && !ins))
+        return fail(MCRT_EINVAL, "sim_create: 0 .. 8 instruments");
+    if ((int)source->L.size() != medium->n_lambda)
+        return fail(MCRT_EINVAL, "sim_create: source and medium disagree on n_lambda");
+    mcrt_options o;
+    mcrt_options_default(&o);
+    if (opt) o = *opt;
+    if (o.precision != MCRT_FP32 && o.precision != MCRT_FP64_VALIDATE)
+        return fail(MCRT_EINVAL, "sim_create: unknown precision");
+    if (!(o.w_min >= 0.0) || !(o.tau_peel_max > 0.0) || o.event_cap < 1)
+        return fail(MCRT_EINVAL, "sim_create: w_min >= 0, tau_peel_max > 0, event_cap >= 1 required");
+    if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64)
+        return fail(MCRT_EINVAL, "sim_create: tuning values out of range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto *s = new mcrt_sim;
+    s->ctx = ctx;
+    s->medium = medium;
+    s->source = source;
+    s->n_ins = n_ins;
+    s->opt = o;
+    long long off = 0;
+    for (int j = 0; j < n_ins; ++j) {
+        if (!ins[j]) {
+            delete s;
+            return fail(MCRT_EINVAL, "sim_create: NULL instrument");
+        }
+        s->ins[j] = ins[j]->h;
+        s->ins_offset[j] = off;
+        off += (long long)medium->n_lambda * ins[j]->h.npix[0] * ins[j]->h.npix[1];
+    }
+    s->image_elems = off;
+    const mcrt_grid *g = medium->grid;
+    int rc = dev_alloc((void **)&s->d_density, (size_t)g->n_cells * sizeof(float));
+    if (!rc) {
+        hipError_t e = hipMemcpy(s->d_density, medium->density.data(), (size_t)g->n_cells * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("density upload: ") + hipGetErrorString(e));
+    }
+    if (!rc && g->type == kOctree) {
+        std::vector<int32_t> node, top;
+        std::string err;
+        int depth = encode_octree((int64_t)g->first_child.size(), g->first_child.data(), g->n_cells, node, err);
+        s->depth = depth;
+        s->top_level = o.top_level >= 0 ? std::min(o.top_level, depth) : std::min(depth, 7);
+        build_top_table(node, s->top_level, top);
+        rc = dev_alloc((void **)&s->d_node, node.size() * sizeof(int32_t));
+        if (!rc) rc = dev_alloc((void **)&s->d_top, top.size() * sizeof(int32_t));
+        if (!rc) {
+            hipError_t e = hipMemcpy(s->d_node, node.data(), node.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(s->d_top, top.data(), top.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("octree upload: ") + hipGetErrorString(e));
+        }
+    }
+    if (!rc) rc = o.precision == MCRT_FP32 ? upload_instruments<float>(s) : upload_instruments<double>(s);
+    if (rc) {
+        sim_free_device(s);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return MCRT_OK;
+}
+
+int mcrt_sim_info(const mcrt_sim *sim, int64_t *n_cells, int32_t *n_lambda, int32_t *n_ins)
+{
+    if (!sim) return fail(MCRT_EINVAL, "sim_info: NULL sim");
+    if (n_cells) *n_cells = sim->medium->grid->n_cells;
+    if (n_lambda) *n_lambda = sim->medium->n_lambda;
+    if (n_ins) *n_ins = sim->n_ins;
+    return MCRT_OK;
+}
+
+static size_t image_bytes(const mcrt_sim *s)
+{
+    return (size_t)s->image_elems * (s->opt.precision == MCRT_FP32 ? sizeof(float) : sizeof(double));
+}
+
+static size_t table_elems(const mcrt_sim *s) { return (size_t)s->medium->grid->n_cells * (size_t)s->medium->n_lambda; }
+
+void mcrt_result_destroy(mcrt_result *res)
+{
+    if (!res) return;
+    (void)hipSetDevice(res->sim->ctx->device);
+    dev_free(res->d_table);
+    dev_free(res->d_images);
+    dev_free(res->d_energy);
+    dev_free(res->d_stats);
+    dev_free(res->d_counter);
+    delete res;
+}
+
+int mcrt_result_zero(mcrt_result *res)
+{
+    if (!res) return fail(MCRT_EINVAL, "result_zero: NULL result");
+    const mcrt_sim *s = res->sim;
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    HIP_TRY(launch_fill_zero(res->d_table, table_elems(s) * sizeof(double), st));
+    HIP_TRY(launch_fill_zero(res->d_images, image_bytes(s), st));
+    HIP_TRY(launch_fill_zero(res->d_energy, 4 * sizeof(double), st));
+    HIP_TRY(launch_fill_zero(res->d_stats, kNumStats * sizeof(unsigned long long), st));
+    HIP_TRY(hipStreamSynchronize(st));
+    res->kernel_ms = 0.0;
+    return MCRT_OK;
+}
+
+int mcrt_result_create(mcrt_sim *sim, mcrt_result **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "result_create: out is NULL");
+    *out = nullptr;
+    if (!sim) return fail(MCRT_EINVAL, "result_create: NULL sim");
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    auto *r = new mcrt_result;
+    r->sim = sim;
+    int rc = dev_alloc((void **)&r->d_table, table_elems(sim) * sizeof(double));
+    if (!rc) rc = dev_alloc(&r->d_images, image_bytes(sim));
+    if (!rc) rc = dev_alloc((void **)&r->d_energy, 4 * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&r->d_stats, kNumStats * sizeof(unsigned long long));
+    if (!rc) rc = dev_alloc((void **)&r->d_counter, sizeof(unsigned long long));
+    if (!rc) rc = mcrt_result_zero(r);
+    if (rc) {
+        std::string msg = g_err;
+        mcrt_result_destroy(r);
+        g_err = msg;
+        return rc;
+    }
+    *out = r;
+    return MCRT_OK;
+}
+
+template <typename Real, typename ImgT>
+static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                    mcrt_result *r)
+{
+    const mcrt_medium *m = s->medium;
+    const mcrt_grid *g = m->grid;
+    hipStream_t st = s->ctx->stream;
+    std::vector<Optics<Real>> optics((size_t)m->n_lambda);
+    for (int l = 0; l < m->n_lambda; ++l) {
+        optics[l].kappa = (Real)m->kappa[l];
+        optics[l].albedo = (Real)m->albedo[l];
+        optics[l].g = (Real)m->g[l];
+        optics[l].L0 = (Real)(s->source->L[l] / (double)n_per_lambda);
+    }
+    HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill_zero(r->d_counter, sizeof(unsigned long long), st));
+
+    TransportArgs<Real, ImgT> a{};
+    View<Real, ImgT> &v = a.view;
+    v.grid_type = g->type;
+    for (int c = 0; c < 3; ++c) {
+        v.n[c] = g->n[c];
+        v.lo[c] = (Real)g->box[c];
+        v.hi[c] = (Real)g->box[3 + c];
+        v.cs[c] = (Real)((g->box[3 + c] - g->box[c]) / (double)g->n[c]);
+    }
+    v.depth = s->depth;
+    v.top_level = s->top_level;
+    v.density = s->d_density;
+    v.node = s->d_node;
+    v.top = s->d_top;
+    v.n_cells = g->n_cells;
+    v.n_lambda = m->n_lambda;
+    v.optics = nullptr;
+    v.src_type = s->source->type;
+    for (int c = 0; c < 3; ++c) v.src_pos[c] = (Real)s->source->pos[c];
+    v.hR = (Real)s->source->hR;
+    v.zs = (Real)s->source->zs;
+    v.n_ins = s->n_ins;
+    v.ins = nullptr;
+    v.table = r->d_table;
+    v.images = (ImgT *)r->d_images;
+    v.w_min = (Real)s->opt.w_min;
+    v.event_cap = s->opt.event_cap;
+    v.tau_peel_max = (Real)s->opt.tau_peel_max;
+    v.octree_guard = 16 * 3 * (1 << s->depth) + 64;
+    v.key0 = (uint32_t)(seed & 0xffffffffu);
+    v.key1 = (uint32_t)(seed >> 32);
+    v.model = 0;
+    a.optics = (const Optics<Real> *)s->d_optics;
+    a.ins = (const InsDesc<Real> *)s->d_ins;
+    a.count = count;
+    a.first_id = first_id;
+    a.total = count * (uint64_t)m->n_lambda;
+    a.chunk = (uint32_t)(s->opt.chunk > 0 ? s->opt.chunk : 256);
+    a.threshold = s->opt.threshold > 0 ? s->opt.threshold : 16;
+    a.counter = r->d_counter;
+    a.energy = r->d_energy;
+    a.stats = r->d_stats;
+    int wpc = s->opt.waves_per_cu > 0 ? s->opt.waves_per_cu : 16;
+    uint64_t waves = (uint64_t)s->ctx->n_cu * (uint64_t)wpc;
+    uint64_t chunks = (a.total + a.chunk - 1) / a.chunk;
+    if (waves > chunks) waves = chunks;
+    int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
+    if (grid < 1) grid = 1;
+
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    hipError_t le;
+    if constexpr (sizeof(Real) == 4) le = launch_transport_f32(a, grid, st);
+    else le = launch_transport_f64(a, grid, st);
+    HIP_TRY(le);
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    r->kernel_ms = ms;
+    unsigned long long stats[kNumStats];
+    HIP_TRY(hipMemcpy(stats, r->d_stats, sizeof(stats), hipMemcpyDeviceToHost));
+    if (stats[7] > 0) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
+    return MCRT_OK;
+}
+
+namespace {
+struct BusyGuard {
+    std::atomic<int> &flag;
+    bool owned;
+    explicit BusyGuard(std::atomic<int> &f) : flag(f)
+    {
+        int expect = 0;
+        owned = flag.compare_exchange_strong(expect, 1);
+    }
+    ~BusyGuard()
+    {
+        if (owned) flag.store(0);
+    }
+};
+} // namespace
+
+int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                  mcrt_result *res)
+{
+    if (!sim || !res) return fail(MCRT_EINVAL, "run_into: NULL sim or result");
+    if (res->sim != sim) return fail(MCRT_EINVAL, "run_into: result belongs to another sim");
+    if (n_per_lambda == 0 || n_per_lambda > (uint64_t(1) << 32))
+        return fail(MCRT_EINVAL, "run_into: n_per_lambda must be in 1 .. 2^32");
+    if (first_id > n_per_lambda || count > n_per_lambda - first_id)
+        return fail(MCRT_EINVAL, "run_into: id range exceeds n_per_lambda");
+    BusyGuard guard(sim->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "run_into: the simulation is already running");
+    if (count == 0) return MCRT_OK;
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    if (sim->opt.precision == MCRT_FP32) return run_impl<float, float>(sim, n_per_lambda, first_id, count, seed, res);
+    return run_impl<double, double>(sim, n_per_lambda, first_id, count, seed, res);
+}
+
+int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                   mcrt_result **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "run_range: out is NULL");
+    *out = nullptr;
+    mcrt_result *r = nullptr;
+    int rc = mcrt_result_create(sim, &r);
+    if (rc) return rc;
+    rc = mcrt_run_into(sim, n_per_lambda, first_id, count, seed, r);
+    if (rc != MCRT_OK && rc != MCRT_ELIMIT) {
+        std::string msg = g_err;
+        mcrt_result_destroy(r);
+        g_err = msg;
+        return rc;
+    }
+    *out = r;
+    return rc;
+}
+
+int mcrt_run(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t seed, mcrt_result **out)
+{
+    return mcrt_run_range(sim, n_per_lambda, 0, n_per_lambda, seed, out);
+}
+
+int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count)
+{
+    if (!res || !out) return fail(MCRT_EINVAL, "result_absorption: NULL argument");
+    const mcrt_sim *s = res->sim;
+    const int64_t nc = s->medium->grid->n_cells;
+    const int nl = s->medium->n_lambda;
+    if (count < table_elems(s)) return fail(MCRT_EINVAL, "result_absorption: output buffer too small");
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    int64_t block = std::max<int64_t>(1, ((int64_t)1 << 25) / nl); // cells per pass (<= 256 MB)
+    if (block > nc) block = nc;
+    double *tmp = nullptr;
+    int rc = dev_alloc((void **)&tmp, (size_t)block * nl * sizeof(double));
+    if (rc) return rc;
+    for (int64_t c0 = 0; c0 < nc; c0 += block) {
+        int64_t n = std::min(block, nc - c0);
+        hipError_t e = launch_table_transpose(res->d_table, tmp, nc, nl, c0, n, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + c0 * nl, tmp, (size_t)n * nl * sizeof(double), hipMemcpyDefault, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            dev_free(tmp);
+            return fail(MCRT_EDEVICE, std::string("result_absorption: ") + hipGetErrorString(e));
+        }
+    }
+    dev_free(tmp);
+    return MCRT_OK;
+}
+
+int mcrt_result_image(const mcrt_result *res, int32_t ins, double *out, size_t count)
+{
+    if (!res || !out) return fail(MCRT_EINVAL, "result_image: NULL argument");
+    const mcrt_sim *s = res->sim;
+    if (ins < 0 || ins >= s->n_ins) return fail(MCRT_EINVAL, "result_image: no such instrument");
+    int64_t n = (int64_t)s->medium->n_lambda * s->ins[ins].npix[0] * s->ins[ins].npix[1];
+    if (count < (size_t)n) return fail(MCRT_EINVAL, "result_image: output buffer too small");
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    double *tmp = nullptr;
+    int rc = dev_alloc((void **)&tmp, (size_t)n * sizeof(double));
+    if (rc) return rc;
+    hipError_t e;
+    if (s->opt.precision == MCRT_FP32)
+        e = launch_image_scale<float>((const float *)res->d_images + s->ins_offset[ins], tmp, n, s->inv4pid2[ins], st);
+    else
+        e = launch_image_scale<double>((const double *)res->d_images + s->ins_offset[ins], tmp, n, s->inv4pid2[ins], st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, (size_t)n * sizeof(double), hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dev_free(tmp);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, std::string("result_image: ") + hipGetErrorString(e));
+    return MCRT_OK;
+}
+
+int mcrt_result_energy(const mcrt_result *res, double *emitted, double *absorbed, double *escaped, double *truncated)
+{
+    if (!res) return fail(MCRT_EINVAL, "result_energy: NULL result");
+    HIP_TRY(hipSetDevice(res->sim->ctx->device));
+    double e[4];
+    HIP_TRY(hipMemcpy(e, res->d_energy, sizeof(e), hipMemcpyDeviceToHost));
+    if (emitted) *emitted = e[0];
+    if (absorbed) *absorbed = e[1];
+    if (escaped) *escaped = e[2];
+    if (truncated) *truncated = e[3];
+    return MCRT_OK;
+}
+
+int mcrt_result_stats(const mcrt_result *res, mcrt_stats *stats)
+{
+    if (!res || !stats) return fail(MCRT_EINVAL, "result_stats: NULL argument");
+    HIP_TRY(hipSetDevice(res->sim->ctx->device));
+    unsigned long long s[kNumStats];
+    HIP_TRY(hipMemcpy(s, res->d_stats, sizeof(s), hipMemcpyDeviceToHost));
+    stats->packets = s[0];
+    stats->events = s[1];
+    stats->prop_cells = s[2];
+    stats->locate_cells = s[3];
+    stats->peel_cells = s[4];
+    stats->peel_adds = s[5];
+    stats->peel_dropped = s[6];
+    stats->capped = s[7];
+    stats->guard = s[8];
+    stats->kernel_ms = res->kernel_ms;
+    return MCRT_OK;
+}
+

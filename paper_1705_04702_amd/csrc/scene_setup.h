@@ -1,0 +1,124 @@
+// scene_setup.h -- host-side preparation of the per-simulation constants the
+// transport lanes read: instrument frames, per-wavelength optics and the
+// octree node encoding.  Shared by the C-ABI library and the host lane
+// simulator so both see identical constants.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mcrt {
+
+struct HostInstrument {
+    double incl_deg, azim_deg, distance, fov[2];
+    int32_t npix[2];
+};
+
+// Distant observer frame (parallel projection): k_obs towards the observer,
+// sky basis e_x = (-sin a, cos a, 0), e_y = (-cos i cos a, -cos i sin a, sin i).
+template <typename Real>
+inline void make_ins_desc(const HostInstrument &h, long long offset, InsDesc<Real> &o, double &inv4pid2)
+{
+    const double pi = 3.14159265358979323846;
+    double i = h.incl_deg * pi / 180.0, a = h.azim_deg * pi / 180.0;
+    double si = std::sin(i), ci = std::cos(i), sa = std::sin(a), ca = std::cos(a);
+    double kobs[3] = {si * ca, si * sa, ci};
+    double ex[3] = {-sa, ca, 0.0};
+    double ey[3] = {-ci * ca, -ci * sa, si};
+    for (int c = 0; c < 3; ++c) {
+        o.kobs[c] = (Real)kobs[c];
+        o.ex[c] = (Real)ex[c];
+        o.ey[c] = (Real)ey[c];
+    }
+    o.half_fovx = (Real)(0.5 * h.fov[0]);
+    o.half_fovy = (Real)(0.5 * h.fov[1]);
+    o.pixx = (Real)(h.fov[0] / (double)h.npix[0]);
+    o.pixy = (Real)(h.fov[1] / (double)h.npix[1]);
+    o.nx = h.npix[0];
+    o.ny = h.npix[1];
+    o.offset = offset;
+    inv4pid2 = 1.0 / (4.0 * pi * h.distance * h.distance);
+}
+
+// Encodes an octree given as first_child (-1 for leaves, children contiguous
+// in the order c = bx + 2 by + 4 bz) into node values: >= 0 first child,
+// < 0 -(leaf + 1), leaves numbered in depth-first order.  Returns the depth,
+// or -1 with a message if the tree is malformed.
+inline int encode_octree(int64_t n_nodes, const int32_t *first_child, int64_t n_cells,
+                         std::vector<int32_t> &node, std::string &err)
+{
+    if (n_nodes <= 0 || n_nodes >= (int64_t(1) << 27)) {
+        err = "octree: node count out of range (1 .. 2^27-1)";
+        return -1;
+    }
+    node.assign((size_t)n_nodes, 0);
+    std::vector<uint8_t> seen((size_t)n_nodes, 0);
+    std::vector<std::pair<int64_t, int>> stack;
+    stack.reserve(1024);
+    stack.push_back({0, 0});
+    seen[0] = 1;
+    int64_t next_leaf = 0;
+    int depth = 0;
+    while (!stack.empty()) {
+        auto [nd, level] = stack.back();
+        stack.pop_back();
+        int32_t fc = first_child[nd];
+        if (fc < 0) {
+            node[(size_t)nd] = (int32_t)(-(next_leaf + 1));
+            next_leaf++;
+            if (level > depth) depth = level;
+        } else {
+            if ((int64_t)fc + 7 >= n_nodes || fc <= nd) {
+                err = "octree: first_child out of range";
+                return -1;
+            }
+            if (level + 1 > 15) {
+                err = "octree: depth exceeds 15";
+                return -1;
+            }
+            node[(size_t)nd] = fc;
+            for (int c = 7; c >= 0; --c) {
+                if (seen[(size_t)fc + c]) {
+                    err = "octree: node reachable twice";
+                    return -1;
+                }
+                seen[(size_t)fc + c] = 1;
+                stack.push_back({(int64_t)fc + c, level + 1});
+            }
+        }
+    }
+    if (next_leaf != n_cells) {
+        err = "octree: leaf count does not match the density array";
+        return -1;
+    }
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (!seen[(size_t)i]) {
+            err = "octree: unreachable node";
+            return -1;
+        }
+    return depth;
+}
+
+// Dense top table of the octree at level top_level: for each block the
+// deepest node at or above that level containing it, packed (level << 27) | node.
+inline void build_top_table(const std::vector<int32_t> &node, int top_level, std::vector<int32_t> &top)
+{
+    int T = 1 << top_level;
+    top.assign((size_t)T * T * T, 0);
+    for (int bz = 0; bz < T; ++bz)
+        for (int by = 0; by < T; ++by)
+            for (int bx = 0; bx < T; ++bx) {
+                int nd = 0, level = 0;
+                while (level < top_level && node[(size_t)nd] >= 0) {
+                    int bit = top_level - 1 - level;
+                    int child = ((bx >> bit) & 1) + 2 * ((by >> bit) & 1) + 4 * ((bz >> bit) & 1);
+                    nd = node[(size_t)nd] + child;
+                    level++;
+                }
+                top[((size_t)bz * T + by) * T + bx] = (level << 27) | nd;
+            }
+}
+
+} // namespace mcrt

@@ -1,0 +1,676 @@
+// transport_core.h -- per-lane logic of the Monte Carlo photon-packet life
+// cycle (stellar emission phase of the hybrid-parallel SKIRT paper, Section
+// 3.2; accumulation as in Section 5.2 "Lockfree additions").
+//
+// Everything here acts on ONE packet held in registers by one lane; the
+// persistent wave scheduler (transport_kernel.h) decides when each lane
+// steps its ray march and when it processes the end of a march.  The header
+// is written against a policy `Sink` that performs the shared-table and image
+// additions (hardware atomics on the GPU), so the same lane code can also be
+// instantiated serially for host-side checking.  The includer defines MCRT_HD
+// (function qualifiers) before including this file.
+//
+// Templates are instantiated for Real = float (production: FP32 transport,
+// FP64 table totals and energy sums) and Real = double (validation mode,
+// same operation order as an FP64 reference, no contraction).
+#pragma once
+
+#include <stdint.h>
+
+#include "det_math.h"
+
+namespace mcrt {
+
+constexpr int kMaxIns = 8;        // instruments per simulation
+constexpr int kMaxLdsLambda = 256; // per-wavelength optics staged in LDS
+
+enum Mode : int {
+    kDead = 0,      // no packet (needs a refill)
+    kPeelEmit = 1,  // emission peel-off march towards instrument j
+    kProp = 2,      // propagation march with continuous absorption
+    kLocate = 3,    // second march to the forced interaction point
+    kPeelScat = 4,  // scattering peel-off march towards instrument j
+};
+
+enum GridType : int { kCartesian = 0, kOctree = 1 };
+enum SourceType : int { kPointIso = 0, kPointAniso = 1, kExpDisk = 2 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): counter (block, packet, wavelength,
+// model), key (seed low, seed high).  Slot s of a packet uses block s/2 and
+// the word pair (2(s%2), 2(s%2)+1) as (high, low).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+MCRT_HD U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Open-interval uniforms from a (high, low) word pair.
+template <typename Real> struct Uni;
+template <> struct Uni<float> {
+    MCRT_HD static float from(uint32_t hi, uint32_t) { return ((float)(hi >> 9) + 0.5f) * 0x1p-23f; }
+};
+template <> struct Uni<double> {
+    MCRT_HD static double from(uint32_t hi, uint32_t lo)
+    {
+        uint64_t w = ((uint64_t)hi << 32) | (uint64_t)lo;
+        return ((double)(w >> 12) + 0.5) * 0x1p-52;
+    }
+};
+
+struct Stream {
+    uint32_t k0, k1, packet, lambda, model;
+    // the two uniforms of block b: slots 2b and 2b+1
+    template <typename Real> MCRT_HD void pair(uint32_t block, Real &a, Real &b) const
+    {
+        U4 o = philox(block, packet, lambda, model, k0, k1);
+        a = Uni<Real>::from(o.x, o.y);
+        b = Uni<Real>::from(o.z, o.w);
+    }
+    template <typename Real> MCRT_HD Real slot(uint32_t s) const
+    {
+        U4 o = philox(s >> 1, packet, lambda, model, k0, k1);
+        return (s & 1u) ? Uni<Real>::from(o.z, o.w) : Uni<Real>::from(o.x, o.y);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Scene views
+// ---------------------------------------------------------------------------
+template <typename Real> struct InsDesc {
+    Real kobs[3], ex[3], ey[3];
+    Real half_fovx, half_fovy, pixx, pixy; // pixel size = fov / npix
+    int nx, ny;
+    long long offset; // first image element of this instrument
+};
+
+template <typename Real> struct Optics {
+    Real kappa, albedo, g, L0;
+};
+
+template <typename Real, typename ImgT> struct View {
+    // grid
+    int grid_type;
+    int n[3];       // cells per axis (Cartesian) or lattice size 2^depth (octree)
+    int depth;      // octree maximum depth
+    int top_level;  // octree: level of the dense top table
+    Real lo[3], hi[3], cs[3];
+    const float *density;
+    const int *node;     // octree: >= 0 first child, < 0 -(leaf + 1)
+    const int *top;      // octree: (level << 27) | node for each top-table block
+    long long n_cells;
+    // per wavelength
+    int n_lambda;
+    const Optics<Real> *optics;
+    // source
+    int src_type;
+    Real src_pos[3];
+    Real hR, zs;
+    // instruments
+    int n_ins;
+    const InsDesc<Real> *ins;
+    // outputs
+    double *table;  // [n_lambda][n_cells]
+    ImgT *images;   // [n_ins][n_lambda][ny][nx], flux * 4 pi d^2
+    // options
+    Real w_min;
+    long long event_cap;
+    Real tau_peel_max;
+    int octree_guard;
+    uint32_t key0, key1, model;
+};
+
+// Per-lane tallies, reduced once per wave at the end of the kernel.
+struct Tally {
+    double emitted, absorbed, escaped, truncated;
+    uint32_t packets, events, prop_cells, locate_cells, peel_cells, peel_adds, peel_dropped, capped, guard;
+};
+
+template <typename Real> struct Lane {
+    Real r[3], k[3];    // packet position and direction
+    Real d[3], id3[3];  // march direction and its reciprocal
+    Real tn[3];         // Cartesian: ray parameter of the next plane per axis
+    Real t;             // ray parameter at the start of the current segment
+    Real L, L0;         // current luminosity, launch luminosity
+    Real wpeel;         // peel-off luminosity times phase
+    Real E, tau, wabs, tau_int;
+    Real a_t0, a_tau, a_kr, a_ds; // locate: last segment with positive optical depth
+    Optics<Real> opt;
+    int ci[3];          // cell index (Cartesian) or lattice cursor (octree)
+    int mode, j, nseg, steps;
+    long long e;
+    uint32_t id, lam;
+    bool marching, found, dropped;
+};
+
+// ---------------------------------------------------------------------------
+// Precision traits: FP64 divides exactly like the reference; FP32 multiplies
+// by the reciprocal of the direction.
+// ---------------------------------------------------------------------------
+template <typename Real> struct Prec;
+template <> struct Prec<float> {
+    MCRT_HD static float over_k(float num, float k, float ik) { return num * ik; }
+    MCRT_HD static float inf() { return __builtin_huge_valf(); }
+};
+template <> struct Prec<double> {
+    MCRT_HD static double over_k(double num, double k, double) { return num / k; }
+    MCRT_HD static double inf() { return __builtin_huge_val(); }
+};
+
+template <typename Real> MCRT_HD Real rmax(Real a, Real b) { return a > b ? a : b; }
+
+// Elementary functions: the device math library in FP32; in FP64 the
+// fixed-sequence implementations of det_math.h.
+template <typename Real> struct Math;
+template <> struct Math<float> {
+    MCRT_HD static float e_exp(float x) { return exp(x); }
+    MCRT_HD static float e_expm1(float x) { return expm1(x); }
+    MCRT_HD static float e_log(float x) { return log(x); }
+    MCRT_HD static float e_log1p(float x) { return log1p(x); }
+    MCRT_HD static float e_atanh(float x) { return atanh(x); }
+    MCRT_HD static void e_sincos(float x, float &s, float &c)
+    {
+        s = sin(x);
+        c = cos(x);
+    }
+};
+template <> struct Math<double> {
+    MCRT_HD static double e_exp(double x) { return dm::exp(x); }
+    MCRT_HD static double e_expm1(double x) { return dm::expm1(x); }
+    MCRT_HD static double e_log(double x) { return dm::log(x); }
+    MCRT_HD static double e_log1p(double x) { return dm::log1p(x); }
+    MCRT_HD static double e_atanh(double x) { return dm::atanh(x); }
+    MCRT_HD static void e_sincos(double x, double &s, double &c) { dm::sincos(x, s, c); }
+};
+
+// Slice containing coordinate p; a point on a plane that the ray leaves
+// downwards belongs to the slice below.
+template <typename Real> MCRT_HD int slice_index(Real p, Real lo, Real cs, int n, Real k)
+{
+    Real q = floor((p - lo) / cs);
+    int i;
+    if (q < Real(0)) i = 0;
+    else if (q > Real(n - 1)) i = n - 1;
+    else i = (int)q;
+    if (p == lo + (Real)i * cs && k < Real(0)) i -= 1;
+    return i;
+}
+
+// Start of the ray r + t d (t >= 0) in the grid box: t0 and slice indices.
+template <typename Real, typename ImgT>
+MCRT_HD bool ray_start(const View<Real, ImgT> &v, const Real r[3], const Real d[3], Real &t0, int idx[3])
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!(r[a] >= v.lo[a] && r[a] <= v.hi[a])) inside = false;
+    if (inside) {
+        t0 = Real(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) idx[a] = slice_index(r[a], v.lo[a], v.cs[a], v.n[a], d[a]);
+    } else {
+        Real tn = -Prec<Real>::inf(), tf = Prec<Real>::inf();
+        int entry = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (d[a] == Real(0)) {
+                if (r[a] < v.lo[a] || r[a] > v.hi[a]) return false;
+            } else {
+                Real t1 = (v.lo[a] - r[a]) / d[a];
+                Real t2 = (v.hi[a] - r[a]) / d[a];
+                Real nr = t1 < t2 ? t1 : t2;
+                Real fr = t1 < t2 ? t2 : t1;
+                if (nr > tn) {
+                    tn = nr;
+                    entry = a;
+                }
+                if (fr < tf) tf = fr;
+            }
+        }
+        if (entry < 0 || tn > tf || tf < Real(0) || tn < Real(0)) return false;
+        t0 = tn;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == entry) {
+                idx[a] = d[a] > Real(0) ? 0 : v.n[a] - 1;
+            } else {
+                Real p = r[a] + tn * d[a];
+                idx[a] = slice_index(p, v.lo[a], v.cs[a], v.n[a], d[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (idx[a] < 0 || idx[a] >= v.n[a]) return false;
+    return true;
+}
+
+template <typename Real, typename ImgT>
+MCRT_HD Real plane_t(const View<Real, ImgT> &v, const Lane<Real> &ln, int a, int j)
+{
+    return Prec<Real>::over_k(v.lo[a] + (Real)j * v.cs[a] - ln.r[a], ln.d[a], ln.id3[a]);
+}
+
+template <typename Real, typename ImgT>
+MCRT_HD Real next_plane_t(const View<Real, ImgT> &v, const Lane<Real> &ln, int a)
+{
+    if (ln.d[a] > Real(0)) return plane_t(v, ln, a, ln.ci[a] + 1);
+    if (ln.d[a] < Real(0)) return plane_t(v, ln, a, ln.ci[a]);
+    return Prec<Real>::inf();
+}
+
+// Begins a march from the packet position along direction dir.
+template <typename Real, typename ImgT>
+MCRT_HD void begin_march(const View<Real, ImgT> &v, Lane<Real> &ln, const Real dir[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ln.d[a] = dir[a];
+        ln.id3[a] = dir[a] != Real(0) ? Real(1) / dir[a] : Real(0);
+    }
+    ln.nseg = 0;
+    ln.steps = 0;
+    ln.tau = Real(0);
+    Real t0;
+    ln.marching = ray_start(v, ln.r, ln.d, t0, ln.ci);
+    ln.t = t0;
+    if (ln.marching && v.grid_type == kCartesian) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ln.tn[a] = next_plane_t(v, ln, a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One segment of the march: finds the cell and its path length, then applies
+// the mode's action (deposit, optical-depth sum, interaction search).
+// ---------------------------------------------------------------------------
+template <typename Real, typename ImgT, typename Sink>
+MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    // All per-axis arrays are indexed with compile-time constants (unrolled
+    // loops with `a == am` tests) so that the lane state stays in registers.
+    int cell;
+    Real te;
+    bool exits = false;
+    if (v.grid_type == kCartesian) {
+        Real tmin = ln.tn[0];
+        int am = 0;
+        if (ln.tn[1] < tmin) {
+            tmin = ln.tn[1];
+            am = 1;
+        }
+        if (ln.tn[2] < tmin) {
+            tmin = ln.tn[2];
+            am = 2;
+        }
+        te = rmax(tmin, ln.t);
+        cell = ln.ci[0] + v.n[0] * (ln.ci[1] + v.n[1] * ln.ci[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == am) {
+                ln.ci[a] += ln.d[a] > Real(0) ? 1 : -1;
+                exits = ln.ci[a] < 0 || ln.ci[a] >= v.n[a];
+                if (!exits) ln.tn[a] = next_plane_t(v, ln, a);
+            }
+        }
+    } else {
+        // locate the leaf holding lattice point ci: dense top table, then descend
+        const int sh = v.depth - v.top_level;
+        const int T = 1 << v.top_level;
+        int packed = v.top[((ln.ci[2] >> sh) * T + (ln.ci[1] >> sh)) * T + (ln.ci[0] >> sh)];
+        int level = packed >> 27;
+        int nd = packed & ((1 << 27) - 1);
+        int val = v.node[nd];
+        while (val >= 0) {
+            int bit = v.depth - 1 - level;
+            int child = ((ln.ci[0] >> bit) & 1) + 2 * ((ln.ci[1] >> bit) & 1) + 4 * ((ln.ci[2] >> bit) & 1);
+            nd = val + child;
+            val = v.node[nd];
+            level++;
+        }
+        cell = -val - 1;
+        const int size = 1 << (v.depth - level);
+        int o[3];
+        Real tn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = ln.ci[a] & ~(size - 1);
+            if (ln.d[a] > Real(0)) tn[a] = plane_t(v, ln, a, o[a] + size);
+            else if (ln.d[a] < Real(0)) tn[a] = plane_t(v, ln, a, o[a]);
+            else tn[a] = Prec<Real>::inf();
+        }
+        Real tmin = tn[0];
+        int am = 0;
+        if (tn[1] < tmin) {
+            tmin = tn[1];
+            am = 1;
+        }
+        if (tn[2] < tmin) {
+            tmin = tn[2];
+            am = 2;
+        }
+        te = rmax(tmin, ln.t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == am) {
+                int q = ln.d[a] > Real(0) ? o[a] + size : o[a] - 1;
+                exits = q < 0 || q >= v.n[a];
+                ln.ci[a] = q;
+            } else {
+                Real p = ln.r[a] + te * ln.d[a];
+                Real qf = floor((p - v.lo[a]) / v.cs[a]);
+                int qi;
+                if (qf < Real(o[a])) qi = o[a];
+                else if (qf > Real(o[a] + size - 1)) qi = o[a] + size - 1;
+                else qi = (int)qf;
+                ln.ci[a] = qi;
+            }
+        }
+        if (++ln.steps >= v.octree_guard) {
+            exits = true;
+            ty.guard++;
+        }
+    }
+    const Real ds = te - ln.t;
+    const Real t_start = ln.t;
+    ln.t = te;
+    ln.nseg++;
+    const Real kr = ln.opt.kappa * (Real)v.density[cell];
+    const Real dtau = kr * ds;
+    if (ln.mode == kProp) {
+        Real x = -Math<Real>::e_expm1(-dtau);
+        Real A = ln.wabs * ln.E * x;
+        sink.deposit(v.table + (long long)ln.lam * v.n_cells + cell, (double)A);
+        ty.absorbed += (double)A;
+        ln.E = ln.E * (Real(1) - x);
+        ln.tau = ln.tau + dtau;
+        ty.prop_cells++;
+    } else if (ln.mode == kLocate) {
+        ty.locate_cells++;
+        Real tprev = ln.tau;
+        ln.tau = ln.tau + dtau;
+        if (dtau > Real(0)) {
+            ln.a_t0 = t_start;
+            ln.a_tau = tprev;
+            ln.a_kr = kr;
+            ln.a_ds = ds;
+        }
+        if (ln.tau >= ln.tau_int) {
+            ln.found = true;
+            exits = true;
+        }
+    } else {
+        ln.tau = ln.tau + dtau;
+        ty.peel_cells++;
+        if (ln.tau >= v.tau_peel_max) {
+            ln.dropped = true;
+            exits = true;
+        }
+    }
+    if (exits) ln.marching = false;
+}
+
+// ---------------------------------------------------------------------------
+// Event processing between marches.
+// ---------------------------------------------------------------------------
+template <typename Real> MCRT_HD Real hg_phase(Real g, Real mu)
+{
+    Real num = Real(1) - g * g;
+    Real den = Real(1) + g * g - Real(2) * g * mu;
+    return num / (den * sqrt(den));
+}
+
+template <typename Real> MCRT_HD Real hg_sample(Real g, Real u)
+{
+    Real mu;
+    if (fabs(g) >= Real(1e-6)) {
+        Real q = (Real(1) - g * g) / (Real(1) - g + Real(2) * g * u);
+        mu = (Real(1) + g * g - q * q) / (Real(2) * g);
+    } else {
+        mu = Real(2) * u - Real(1);
+    }
+    if (mu < Real(-1)) mu = Real(-1);
+    if (mu > Real(1)) mu = Real(1);
+    return mu;
+}
+
+template <typename Real>
+MCRT_HD void rotate_about_pole(Real a, Real b, Real c, Real mu, Real st, Real cp, Real sp, Real &x, Real &y, Real &z)
+{
+    Real s = sqrt(Real(1) - c * c);
+    x = mu * a + st * (a * c * cp - b * sp) / s;
+    y = mu * b + st * (b * c * cp + a * sp) / s;
+    z = mu * c - st * s * cp;
+}
+
+// New direction at polar cosine mu and azimuth phi about k (the x axis
+// replaces z as the azimuth reference within 0.00447 rad of the z axis).
+template <typename Real> MCRT_HD void rotate(Real k[3], Real mu, Real phi)
+{
+    Real st = sqrt(rmax(Real(0), Real(1) - mu * mu));
+    Real sp, cp;
+    Math<Real>::e_sincos(phi, sp, cp);
+    Real x, y, z;
+    if (fabs(k[2]) < Real(0.99999)) {
+        rotate_about_pole(k[0], k[1], k[2], mu, st, cp, sp, x, y, z);
+    } else {
+        Real px, py, pz;
+        rotate_about_pole(k[1], k[2], k[0], mu, st, cp, sp, py, pz, px);
+        x = px;
+        y = py;
+        z = pz;
+    }
+    Real nrm = sqrt(x * x + y * y + z * z);
+    k[0] = x / nrm;
+    k[1] = y / nrm;
+    k[2] = z / nrm;
+}
+
+template <typename Real> struct Consts {
+    MCRT_HD static Real two_pi() { return Real(6.283185307179586476925286766559); }
+};
+
+template <typename Real, typename ImgT>
+MCRT_HD Stream stream_of(const View<Real, ImgT> &v, const Lane<Real> &ln)
+{
+    return Stream{v.key0, v.key1, ln.id, ln.lam, v.model};
+}
+
+template <typename Real, typename ImgT>
+MCRT_HD void begin_peel(const View<Real, ImgT> &v, Lane<Real> &ln, int j, bool emission)
+{
+    ln.mode = emission ? kPeelEmit : kPeelScat;
+    ln.j = j;
+    ln.dropped = false;
+    const InsDesc<Real> &in = v.ins[j];
+    Real w;
+    if (emission) {
+        Real s = v.src_type == kPointAniso ? Real(2) * fabs(in.kobs[2]) : Real(1);
+        w = ln.L0 * s;
+    } else {
+        Real mu = ln.k[0] * in.kobs[0] + ln.k[1] * in.kobs[1] + ln.k[2] * in.kobs[2];
+        w = ln.L * hg_phase(ln.opt.g, mu);
+    }
+    ln.wpeel = w;
+    begin_march(v, ln, in.kobs);
+}
+
+template <typename Real, typename ImgT>
+MCRT_HD void begin_prop(const View<Real, ImgT> &v, Lane<Real> &ln)
+{
+    ln.mode = kProp;
+    ln.wabs = (Real(1) - ln.opt.albedo) * ln.L;
+    ln.E = Real(1);
+    begin_march(v, ln, ln.k);
+}
+
+template <typename Real, typename ImgT>
+MCRT_HD void begin_locate(const View<Real, ImgT> &v, Lane<Real> &ln)
+{
+    ln.mode = kLocate;
+    ln.found = false;
+    begin_march(v, ln, ln.k);
+}
+
+// Scattering: new HG direction, then the next propagation (or the event cap).
+template <typename Real, typename ImgT>
+MCRT_HD void scatter(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty)
+{
+    Stream st = stream_of(v, ln);
+    Real u1 = st.template slot<Real>((uint32_t)(8 * ln.e + 1));
+    Real u2 = st.template slot<Real>((uint32_t)(8 * ln.e + 2));
+    Real mu = hg_sample(ln.opt.g, u1);
+    Real phi = Consts<Real>::two_pi() * u2;
+    rotate(ln.k, mu, phi);
+    ln.e = ln.e + 1;
+    if (ln.e > v.event_cap) {
+        ty.truncated += (double)ln.L;
+        ty.capped++;
+        ln.mode = kDead;
+        ln.marching = false;
+        return;
+    }
+    begin_prop(v, ln);
+}
+
+// Launches packet (lam, id): position, direction, emission peel-offs.
+template <typename Real, typename ImgT>
+MCRT_HD void launch(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id)
+{
+    ln.lam = lam;
+    ln.id = id;
+    ln.opt = v.optics[lam];
+    Stream st = stream_of(v, ln);
+    if (v.src_type == kExpDisk) {
+        Real u0, u1, u2, u3;
+        st.template pair<Real>(0, u0, u1);
+        st.template pair<Real>(1, u2, u3);
+        Real R = -v.hR * Math<Real>::e_log(u0 * u1);
+        Real phi = Consts<Real>::two_pi() * u2;
+        Real z = v.zs * Math<Real>::e_atanh(Real(2) * u3 - Real(1));
+        Real sphi, cphi;
+        Math<Real>::e_sincos(phi, sphi, cphi);
+        ln.r[0] = R * cphi;
+        ln.r[1] = R * sphi;
+        ln.r[2] = z;
+    } else {
+        ln.r[0] = v.src_pos[0];
+        ln.r[1] = v.src_pos[1];
+        ln.r[2] = v.src_pos[2];
+    }
+    Real u4, u5, u6, u7;
+    st.template pair<Real>(2, u4, u5);
+    st.template pair<Real>(3, u6, u7);
+    Real mu;
+    if (v.src_type == kPointAniso) mu = u5 < Real(0.5) ? sqrt(Real(2) * u5) : -sqrt(Real(2) * u5 - Real(1));
+    else mu = Real(2) * u5 - Real(1);
+    Real phi = Consts<Real>::two_pi() * u6;
+    Real s = sqrt(rmax(Real(0), Real(1) - mu * mu));
+    Real sphi, cphi;
+    Math<Real>::e_sincos(phi, sphi, cphi);
+    ln.k[0] = s * cphi;
+    ln.k[1] = s * sphi;
+    ln.k[2] = mu;
+    ln.L0 = ln.opt.L0;
+    ln.L = ln.L0;
+    ln.e = 1;
+    ty.emitted += (double)ln.L0;
+    ty.packets++;
+    if (v.n_ins > 0) begin_peel(v, ln, 0, true);
+    else begin_prop(v, ln);
+}
+
+// Handles the end of a march; leaves the lane marching again or dead.
+template <typename Real, typename ImgT, typename Sink>
+MCRT_HD void finish_march(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    if (ln.mode == kPeelEmit || ln.mode == kPeelScat) {
+        const InsDesc<Real> &in = v.ins[ln.j];
+        if (ln.dropped) {
+            ty.peel_dropped++;
+        } else {
+            Real x = ln.r[0] * in.ex[0] + ln.r[1] * in.ex[1] + ln.r[2] * in.ex[2];
+            Real y = ln.r[0] * in.ey[0] + ln.r[1] * in.ey[1] + ln.r[2] * in.ey[2];
+            Real px = floor((x + in.half_fovx) / in.pixx);
+            Real py = floor((y + in.half_fovy) / in.pixy);
+            if (px >= Real(0) && px < Real(in.nx) && py >= Real(0) && py < Real(in.ny)) {
+                long long idx = in.offset + ((long long)ln.lam * in.ny + (long long)py) * in.nx + (long long)px;
+                sink.pixel(v.images + idx, (ImgT)(ln.wpeel * Math<Real>::e_exp(-ln.tau)));
+                ty.peel_adds++;
+            }
+        }
+        int j = ln.j + 1;
+        bool emission = ln.mode == kPeelEmit;
+        if (j < v.n_ins) {
+            begin_peel(v, ln, j, emission);
+        } else if (emission) {
+            begin_prop(v, ln);
+        } else {
+            scatter(v, ln, ty);
+        }
+        return;
+    }
+    if (ln.mode == kProp) {
+        const Real Epath = ln.E;
+        ty.escaped += (double)(ln.L * Epath);
+        if (ln.nseg == 0 || ln.opt.albedo == Real(0) || ln.tau == Real(0)) {
+            ln.mode = kDead;
+            return;
+        }
+        Real Ls = ln.opt.albedo * ln.L * (Real(1) - Epath);
+        if (Ls < v.w_min * ln.L0) {
+            ty.truncated += (double)Ls;
+            ln.mode = kDead;
+            return;
+        }
+        Stream st = stream_of(v, ln);
+        Real u = st.template slot<Real>((uint32_t)(8 * ln.e + 0));
+        ln.tau_int = -Math<Real>::e_log1p(-u * (Real(1) - Epath));
+        ln.L = Ls;
+        begin_locate(v, ln);
+        return;
+    }
+    if (ln.mode == kLocate) {
+        Real inside = (ln.tau_int - ln.a_tau) / ln.a_kr;
+        if (inside < Real(0)) inside = Real(0);
+        if (inside > ln.a_ds) inside = ln.a_ds;
+        Real dist = ln.a_t0 + inside;
+        ln.r[0] = ln.r[0] + ln.k[0] * dist;
+        ln.r[1] = ln.r[1] + ln.k[1] * dist;
+        ln.r[2] = ln.r[2] + ln.k[2] * dist;
+        ty.events++;
+        if (v.n_ins > 0) begin_peel(v, ln, 0, false);
+        else scatter(v, ln, ty);
+        return;
+    }
+    ln.mode = kDead;
+}
+
+template <typename Real, typename ImgT, typename Sink>
+MCRT_HD void settle(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
+}
+
+} // namespace mcrt

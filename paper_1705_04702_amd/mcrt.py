@@ -1,0 +1,335 @@
+"""Python binding of the C-ABI in include/mcrt.h (ctypes; argument marshalling
+only -- every step of the photon life cycle runs in the HIP kernels of
+libmcrt.so).  PyTorch supplies the stream (and, optionally, device output
+buffers); the library allocates its own device memory.
+
+The binding fails loudly when libmcrt.so is missing: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import weakref
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcrt.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ELIMIT = 0, -1, -2, -3, -4, -5
+FP32, FP64_VALIDATE = 0, 1
+
+EXPORTS = [
+    "mcrt_options_default", "mcrt_context_create", "mcrt_context_destroy",
+    "mcrt_grid_create_cartesian", "mcrt_grid_create_octree", "mcrt_grid_destroy",
+    "mcrt_medium_create", "mcrt_medium_destroy", "mcrt_source_create_point",
+    "mcrt_source_create_expdisk", "mcrt_source_destroy", "mcrt_instrument_create",
+    "mcrt_instrument_destroy", "mcrt_sim_create", "mcrt_sim_destroy", "mcrt_result_create",
+    "mcrt_result_zero", "mcrt_run_into", "mcrt_run", "mcrt_run_range", "mcrt_result_absorption",
+    "mcrt_result_image", "mcrt_result_energy", "mcrt_result_stats", "mcrt_result_destroy",
+    "mcrt_sim_info", "mcrt_last_error",
+]
+
+
+class MCRTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mcrt error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("w_min", ctypes.c_double),
+        ("event_cap", ctypes.c_int64),
+        ("tau_peel_max", ctypes.c_double),
+        ("chunk", ctypes.c_int32),
+        ("waves_per_cu", ctypes.c_int32),
+        ("threshold", ctypes.c_int32),
+        ("top_level", ctypes.c_int32),
+    ]
+
+
+STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
+               "peel_dropped", "capped", "guard"]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in STAT_FIELDS] + [("kernel_ms", ctypes.c_double)]
+
+
+_lib = None
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+DP = ctypes.POINTER(ctypes.c_double)
+FP = ctypes.POINTER(ctypes.c_float)
+IP = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Loads libmcrt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1705_04702_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "mcrt_options_default": (None, [ctypes.POINTER(Options)]),
+        "mcrt_context_create": (ctypes.c_int, [ctypes.c_int, P, PP]),
+        "mcrt_context_destroy": (None, [P]),
+        "mcrt_grid_create_cartesian": (ctypes.c_int, [P, DP, IP, PP]),
+        "mcrt_grid_create_octree": (ctypes.c_int, [P, DP, ctypes.c_int64, IP, PP]),
+        "mcrt_grid_destroy": (None, [P]),
+        "mcrt_medium_create": (ctypes.c_int, [P, FP, ctypes.c_int32, DP, DP, DP, DP, PP]),
+        "mcrt_medium_destroy": (None, [P]),
+        "mcrt_source_create_point": (ctypes.c_int, [P, DP, ctypes.c_int32, ctypes.c_int32, DP, PP]),
+        "mcrt_source_create_expdisk": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double,
+                                                      ctypes.c_int32, DP, PP]),
+        "mcrt_source_destroy": (None, [P]),
+        "mcrt_instrument_create": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, DP, IP, PP]),
+        "mcrt_instrument_destroy": (None, [P]),
+        "mcrt_sim_create": (ctypes.c_int, [P, P, P, PP, ctypes.c_int32,
+                                           ctypes.POINTER(Options), PP]),
+        "mcrt_sim_destroy": (None, [P]),
+        "mcrt_result_create": (ctypes.c_int, [P, PP]),
+        "mcrt_result_zero": (ctypes.c_int, [P]),
+        "mcrt_run_into": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, P]),
+        "mcrt_run": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, PP]),
+        "mcrt_run_range": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, PP]),
+        "mcrt_result_absorption": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_result_image": (ctypes.c_int, [P, ctypes.c_int32, P, ctypes.c_size_t]),
+        "mcrt_result_energy": (ctypes.c_int, [P, DP, DP, DP, DP]),
+        "mcrt_result_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+        "mcrt_result_destroy": (None, [P]),
+        "mcrt_sim_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+        "mcrt_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise MCRTError(rc, lib().mcrt_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(DP)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().mcrt_options_default(ctypes.byref(o))
+    for k, val in kw.items():
+        if val is not None:
+            setattr(o, k, val)
+    return o
+
+
+def _torch_stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A device and a stream (torch's current stream of that device by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if stream is None:
+            stream = _torch_stream(device)
+        h = ctypes.c_void_p()
+        _check(lib().mcrt_context_create(int(device), stream, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self._objs = []
+
+    def close(self):
+        if self.h:
+            lib().mcrt_context_destroy(self.h)
+            self.h = None
+
+
+class Result:
+    def __init__(self, sim: "Sim", h):
+        self.sim = sim
+        self.h = h
+
+    def zero(self):
+        _check(lib().mcrt_result_zero(self.h))
+
+    def table(self, out=None):
+        """Absorbed luminosity [n_cells, n_lambda] (cell i, wavelength j).
+        out may be a float64 numpy array or a CUDA float64 torch tensor."""
+        n = self.sim.n_cells * self.sim.n_lambda
+        if out is None:
+            out = np.empty((self.sim.n_cells, self.sim.n_lambda), dtype=np.float64)
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else out.ctypes.data
+        _check(lib().mcrt_result_absorption(self.h, ctypes.c_void_p(ptr), n))
+        return out
+
+    def image(self, j: int):
+        nl, ny, nx = self.sim.image_shapes[j]
+        out = np.empty((nl, ny, nx), dtype=np.float64)
+        _check(lib().mcrt_result_image(self.h, int(j), ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def images(self) -> List[np.ndarray]:
+        return [self.image(j) for j in range(len(self.sim.image_shapes))]
+
+    def energy(self) -> np.ndarray:
+        e = [ctypes.c_double() for _ in range(4)]
+        _check(lib().mcrt_result_energy(self.h, *[ctypes.byref(x) for x in e]))
+        return np.array([x.value for x in e])
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().mcrt_result_stats(self.h, ctypes.byref(s)))
+        d = {n: int(getattr(s, n)) for n in STAT_FIELDS}
+        d["kernel_ms"] = float(s.kernel_ms)
+        return d
+
+    def close(self):
+        if self.h:
+            lib().mcrt_result_destroy(self.h)
+            self.h = None
+        self.sim._results.discard(self)
+
+    def __del__(self):
+        try:
+            if self.h and self.sim.h:
+                self.close()
+        except Exception:
+            pass
+
+
+class Sim:
+    """A scene uploaded to the device (grid, medium, source, instruments)."""
+
+    _SRC = {"point_iso": 0, "point_aniso": 1}
+
+    def __init__(self, ctx: Context, scene, precision: int = FP32, **tune):
+        L = lib()
+        self.ctx = ctx
+        self.h = None
+        self._results = weakref.WeakSet()
+        box = (ctypes.c_double * 6)(*[float(x) for x in scene.box])
+        g = ctypes.c_void_p()
+        if scene.grid_type == "octree":
+            fc = np.ascontiguousarray(scene.first_child, dtype=np.int32)
+            _check(L.mcrt_grid_create_octree(ctx.h, box, int(fc.shape[0]),
+                                             fc.ctypes.data_as(IP), ctypes.byref(g)))
+        else:
+            n = (ctypes.c_int32 * 3)(*[int(x) for x in scene.n])
+            _check(L.mcrt_grid_create_cartesian(ctx.h, box, n, ctypes.byref(g)))
+        self.grid = g
+        dens = np.ascontiguousarray(scene.density, dtype=np.float32)
+        kap = np.ascontiguousarray(scene.kappa, dtype=np.float64)
+        alb = np.ascontiguousarray(scene.albedo, dtype=np.float64)
+        gg = np.ascontiguousarray(scene.hg_g, dtype=np.float64)
+        lam = np.ascontiguousarray(scene.lambdas, dtype=np.float64)
+        med = ctypes.c_void_p()
+        _check(L.mcrt_medium_create(g, dens.ctypes.data_as(FP), int(kap.shape[0]), _dptr(lam),
+                                    _dptr(kap), _dptr(alb), _dptr(gg), ctypes.byref(med)))
+        self.medium = med
+        lum = np.ascontiguousarray(scene.lum, dtype=np.float64)
+        src = ctypes.c_void_p()
+        if scene.source == "expdisk":
+            _check(L.mcrt_source_create_expdisk(ctx.h, float(scene.disk_hR), float(scene.disk_zs),
+                                                int(lum.shape[0]), _dptr(lum), ctypes.byref(src)))
+        else:
+            pos = (ctypes.c_double * 3)(*[float(x) for x in scene.src_pos])
+            _check(L.mcrt_source_create_point(ctx.h, pos, self._SRC[scene.source], int(lum.shape[0]),
+                                              _dptr(lum), ctypes.byref(src)))
+        self.source = src
+        self.instruments = []
+        for ins in scene.instruments:
+            h = ctypes.c_void_p()
+            fov = (ctypes.c_double * 2)(float(ins.fov[0]), float(ins.fov[1]))
+            npix = (ctypes.c_int32 * 2)(int(ins.npix[0]), int(ins.npix[1]))
+            _check(L.mcrt_instrument_create(ctx.h, float(ins.incl_deg), float(ins.azim_deg),
+                                            float(ins.distance), fov, npix, ctypes.byref(h)))
+            self.instruments.append(h)
+        arr = (ctypes.c_void_p * max(1, len(self.instruments)))(*[h.value for h in self.instruments])
+        opt = default_options(precision=precision, w_min=scene.w_min, event_cap=scene.event_cap,
+                              tau_peel_max=scene.tau_peel_max, **tune)
+        s = ctypes.c_void_p()
+        _check(L.mcrt_sim_create(ctx.h, med, src, arr, len(self.instruments), ctypes.byref(opt),
+                                 ctypes.byref(s)))
+        self.h = s
+        self.n_cells = int(dens.shape[0])
+        self.n_lambda = int(kap.shape[0])
+        self.image_shapes = [(self.n_lambda, ins.npix[1], ins.npix[0]) for ins in scene.instruments]
+        self.precision = precision
+
+    def new_result(self) -> Result:
+        r = ctypes.c_void_p()
+        _check(lib().mcrt_result_create(self.h, ctypes.byref(r)))
+        res = Result(self, r)
+        self._results.add(res)
+        return res
+
+    def run_into(self, result: Result, n_per_lambda: int, seed: int = 0, first_id: int = 0,
+                 count: Optional[int] = None) -> int:
+        if count is None:
+            count = n_per_lambda - first_id
+        return _check(lib().mcrt_run_into(self.h, int(n_per_lambda), int(first_id), int(count),
+                                          int(seed), result.h), allow=(ELIMIT,))
+
+    def run(self, n_per_lambda: int, seed: int = 0, first_id: int = 0,
+            count: Optional[int] = None) -> Result:
+        res = self.new_result()
+        self.run_into(res, n_per_lambda, seed, first_id, count)
+        return res
+
+    def close(self):
+        """Destroys the sim's results first (a handle must outlive the handles
+        created from it), then the sim and its scene objects."""
+        L = lib()
+        for r in list(getattr(self, "_results", ())):
+            r.close()
+        if getattr(self, "h", None):
+            L.mcrt_sim_destroy(self.h)
+            self.h = None
+        for h in getattr(self, "instruments", []):
+            L.mcrt_instrument_destroy(h)
+        self.instruments = []
+        for name, fn in (("source", L.mcrt_source_destroy), ("medium", L.mcrt_medium_destroy),
+                         ("grid", L.mcrt_grid_destroy)):
+            h = getattr(self, name, None)
+            if h:
+                fn(h)
+                setattr(self, name, None)
+
+
+def run_scene(scene, n_per_lambda: int, seed: int = 0, precision: int = FP32, first_id: int = 0,
+              count=None, ctx: Optional[Context] = None, **tune) -> dict:
+    """One-call helper: uploads the scene, runs it, returns host arrays in the
+    same layout as the oracle (table [n_cells, n_lambda], images list,
+    energy, stats)."""
+    own = ctx is None
+    if own:
+        ctx = Context(0)
+    sim = Sim(ctx, scene, precision, **tune)
+    try:
+        res = sim.run(n_per_lambda, seed, first_id, count)
+        out = {"table": res.table(), "images": res.images(), "energy": res.energy(),
+               "stats": res.stats()}
+        res.close()
+        return out
+    finally:
+        sim.close()
+        if own:
+            ctx.close()

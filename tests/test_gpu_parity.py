@@ -1,0 +1,255 @@
+"""GPU parity: the HIP transport kernel against the FP64 oracle, through the
+C-ABI.
+
+* FP64 validation mode: per cell and per pixel |gpu - oracle| <= 1e-9 |oracle|
+  and identical zero patterns; identical event and cell counters.  The only
+  allowed difference is the order of the atomic additions.
+* FP32 production mode: on cells and pixels with an effective number of
+  contributions >= 10, at most 0.5 % may differ from the oracle by more than
+  3 sigma (sigma from the oracle's per-packet second moments); global sums
+  within 1e-5 relative (1e-4 for images); energy balance within 1e-5.
+"""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04702_amd import mcrt, scenes
+
+pytestmark = pytest.mark.gpu
+
+REL_FP64 = 1e-9
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = mcrt.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_run(ctx, sc, N, seed=0, precision=mcrt.FP64_VALIDATE, first_id=0, count=None, **tune):
+    say(f"run {sc.name} N={N} seed={seed} prec={precision} ids=[{first_id},+{count}) {tune}")
+    return mcrt.run_scene(sc, N, seed=seed, precision=precision, first_id=first_id, count=count,
+                          ctx=ctx, **tune)
+
+
+def assert_fp64_parity(g, o, counters=True):
+    for name, a, b in [("table", g["table"], o["table"])] + [
+            (f"image{j}", x, y) for j, (x, y) in enumerate(zip(g["images"], o["images"]))]:
+        assert np.array_equal(a == 0, b == 0), f"{name}: zero patterns differ"
+        nz = b != 0
+        rel = np.abs(a[nz] - b[nz]) / np.abs(b[nz])
+        say(f"{name}: {nz.sum()} nonzero, max rel err {rel.max() if rel.size else 0:.3e}")
+        assert rel.size == 0 or rel.max() <= REL_FP64, f"{name}: max rel {rel.max()}"
+    # global FP64 sums: the summation order differs (bound ~ N eps)
+    np.testing.assert_allclose(g["energy"], o["energy"], rtol=REL_FP64)
+    if counters:
+        for k in ("packets", "events", "prop_cells", "peel_adds", "peel_dropped", "capped"):
+            assert g["stats"][k] == o["stats"][k], k
+
+
+def assert_fp32_statistical(g, o, N, sigmas=3.0, frac=0.005):
+    e = g["energy"]
+    assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+    assert abs(e[1] - o["energy"][1]) / o["energy"][1] < 1e-5 + 3 * _rel_sigma_total(o, N)
+    pairs = [(g["table"], o["table"], o["table_m2"])] + list(zip(g["images"], o["images"], o["image_m2"]))
+    for a, T, m2 in pairs:
+        var = np.maximum(m2 - T * T / N, 0.0)
+        neff = np.where(m2 > 0, T * T / np.where(m2 > 0, m2, 1.0), 0.0)
+        sel = neff >= 10
+        if sel.sum() == 0:
+            continue
+        bad = np.abs(a[sel] - T[sel]) > sigmas * np.sqrt(var[sel]) + 1e-7 * np.abs(T[sel])
+        assert bad.mean() <= frac, f"{bad.mean()} of {sel.sum()} beyond {sigmas} sigma"
+        assert abs(a.sum() - T.sum()) <= 1e-4 * abs(T.sum()) + 3 * np.sqrt(var.sum())
+
+
+def _rel_sigma_total(o, N):
+    T = o["table"]
+    var = np.maximum(o["table_m2"] - T * T / N, 0).sum()
+    return np.sqrt(var) / max(T.sum(), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+
+def test_sphere_c1_fp64_full(ctx):
+    """Uniform sphere, tau = 1, albedo 0.5, g = 0.5, 32^3 grid, 64^2 image,
+    1e5 packets, seed 0: the whole run matches the oracle."""
+    sc = scenes.sphere()
+    N = 100000
+    o = oracle.run(sc, N, seed=0)
+    g = gpu_run(ctx, sc, N, seed=0)
+    assert_fp64_parity(g, o)
+
+
+def test_sphere_c1_fp32_statistical(ctx):
+    sc = scenes.sphere()
+    N = 100000
+    o = oracle.run(sc, N, seed=0, moments=True)
+    g = gpu_run(ctx, sc, N, seed=0, precision=mcrt.FP32)
+    assert_fp32_statistical(g, o, N)
+
+
+@pytest.mark.parametrize("make,N", [
+    (lambda: scenes.disk((32, 32, 16), 8, 64), 600),
+    (lambda: scenes.torus(6, 5, 4, 128, n_clumps=60), 400),
+    (lambda: scenes.sphere(n=24, tau=6.0, albedo=0.9, g=-0.3, incl_deg=35, azim_deg=80), 3000),
+    (lambda: scenes.uniform_cube(3, 2.0, 0.7, 0.8, src=(0.3, -0.9, 0.99)), 3000),
+])
+def test_fp64_parity_scene_families(ctx, make, N):
+    sc = make()
+    o = oracle.run(sc, N, seed=5)
+    g = gpu_run(ctx, sc, N, seed=5)
+    assert_fp64_parity(g, o)
+
+
+def test_disk_full_grid_fp64_and_fp32(ctx):
+    """The exponential disk at its full 256^3 grid and 3 x 512^2 instruments,
+    on 4 of the 64 wavelengths and a packet subset."""
+    sc = scenes.disk()
+    keep = [0, 21, 42, 63]
+    for f in ("lambdas", "kappa", "albedo", "hg_g", "lum"):
+        setattr(sc, f, getattr(sc, f)[keep])
+    sc.name = "disk256_4l"
+    N = 300
+    o = oracle.run(sc, N, seed=3, moments=True)
+    g = gpu_run(ctx, sc, N, seed=3)
+    assert_fp64_parity(g, o)
+    g32 = gpu_run(ctx, sc, N, seed=3, precision=mcrt.FP32)
+    e = g32["energy"]
+    assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+
+
+def test_ragged_ranges_and_split_runs_add(ctx):
+    sc = scenes.disk((16, 16, 8), 3, 32)
+    N = 1000
+    o = oracle.run(sc, N, seed=8, first_id=123, count=777)
+    g = gpu_run(ctx, sc, N, seed=8, first_id=123, count=777, chunk=37)
+    assert_fp64_parity(g, o)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE, chunk=64)
+    try:
+        full = sim.run(N, 8)
+        part = sim.new_result()
+        sim.run_into(part, N, 8, 0, 401)
+        sim.run_into(part, N, 8, 401, 599)
+        np.testing.assert_allclose(part.table(), full.table(), rtol=1e-12, atol=0)
+        np.testing.assert_allclose(part.image(0), full.image(0), rtol=1e-12, atol=0)
+        np.testing.assert_allclose(part.energy(), full.energy(), rtol=1e-12)
+        empty = sim.new_result()
+        sim.run_into(empty, N, 8, N, 0)
+        assert not empty.table().any() and not empty.energy().any()
+        for r in (full, part, empty):
+            r.close()
+    finally:
+        sim.close()
+
+
+@pytest.mark.parametrize("tune", [dict(chunk=1, threshold=1, waves_per_cu=1),
+                                  dict(chunk=1000, threshold=64, waves_per_cu=2),
+                                  dict(chunk=64, threshold=8, waves_per_cu=32)])
+def test_schedule_invariance(ctx, tune):
+    """Results do not depend on the queue chunk, the compaction threshold or
+    the number of persistent waves (beyond atomic ordering)."""
+    sc = scenes.sphere(n=16, tau=2.0)
+    N = 4000
+    o = oracle.run(sc, N, seed=12)
+    g = gpu_run(ctx, sc, N, seed=12, **tune)
+    assert_fp64_parity(g, o)
+
+
+def test_event_cap_reports_elimit(ctx):
+    sc = scenes.sphere(n=16, tau=4.0, albedo=0.95)
+    sc.event_cap = 1
+    N = 2000
+    o = oracle.run(sc, N, seed=2)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    try:
+        res = sim.new_result()
+        rc = sim.run_into(res, N, 2)
+        assert rc == mcrt.ELIMIT
+        g = {"table": res.table(), "images": res.images(), "energy": res.energy(), "stats": res.stats()}
+        assert g["stats"]["capped"] == o["stats"]["capped"] > 0
+        assert_fp64_parity(g, o)
+        res.close()
+    finally:
+        sim.close()
+
+
+def test_degenerate_media(ctx):
+    # empty medium: everything escapes, the image is the direct light only
+    sc = scenes.sphere(n=8)
+    sc.density = np.zeros_like(sc.density)
+    g = gpu_run(ctx, sc, 500, seed=1)
+    assert g["energy"][2] == pytest.approx(1.0, rel=1e-12) and g["energy"][1] == 0
+    assert np.count_nonzero(g["images"][0]) == 1
+    # no scattering
+    sc = scenes.sphere(n=8, albedo=0.0)
+    o = oracle.run(sc, 500, seed=1)
+    assert_fp64_parity(gpu_run(ctx, sc, 500, seed=1), o)
+    # source outside the grid, no instruments
+    sc = scenes.uniform_cube(2, 1.0, 0.6, 0.2, src=(3.0, 0.2, -0.1))
+    sc.instruments = []
+    o = oracle.run(sc, 2000, seed=4)
+    assert_fp64_parity(gpu_run(ctx, sc, 2000, seed=4), o)
+
+
+def test_errors_are_reported(ctx, monkeypatch):
+    sc = scenes.sphere(n=8)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    try:
+        res = sim.new_result()
+        with pytest.raises(mcrt.MCRTError) as ei:
+            sim.run_into(res, 100, 0, 50, 51)
+        assert ei.value.code == mcrt.EINVAL
+        with pytest.raises(mcrt.MCRTError) as ei:
+            sim.run_into(res, 0, 0)
+        assert ei.value.code == mcrt.EINVAL
+        monkeypatch.setenv("MCRT_DEBUG_FAIL_ALLOC", "1")
+        with pytest.raises(mcrt.MCRTError) as ei:
+            sim.new_result()
+        assert ei.value.code == mcrt.ENOMEM
+        monkeypatch.delenv("MCRT_DEBUG_FAIL_ALLOC")
+        res.close()
+    finally:
+        sim.close()
+
+
+def test_concurrent_run_is_busy(ctx):
+    """A second run on a sim that is still running is refused with EBUSY."""
+    sc = scenes.disk((64, 64, 32), 16, 64)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    try:
+        r1, r2 = sim.new_result(), sim.new_result()
+        out = {}
+
+        def long_run():
+            out["rc"] = sim.run_into(r1, 4000000, 0)
+
+        t = threading.Thread(target=long_run)
+        t.start()
+        busy = 0
+        while t.is_alive() and busy == 0:
+            try:
+                sim.run_into(r2, 10, 0)
+            except mcrt.MCRTError as e:
+                assert e.code == mcrt.EBUSY
+                busy += 1
+            time.sleep(0.01)
+        t.join()
+        assert busy == 1
+        assert out["rc"] == mcrt.OK
+        r1.close()
+        r2.close()
+    finally:
+        sim.close()

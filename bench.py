@@ -107,6 +107,21 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
                       f"{cores} processes"}
 
 
+def microbenchmarks():
+    """Random-access rates at the working-set sizes of the workloads."""
+    from paper_1705_04702_amd import mcrt
+    out = {}
+    for mb in (2, 64, 256, 1024, 8192):
+        b = mb << 20
+        row = {}
+        for kind in ("gather4", "atomic_f64", "atomic_f64_wg", "atomic_f32", "atomic_f64_run4"):
+            row[kind] = mcrt.microbench(kind, b, 1 << 28)
+        row["copy_Bps"] = mcrt.microbench("copy", b)
+        out[f"{mb}MiB"] = row
+        print(f"[microbench] {mb} MiB {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,13 +129,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="disk")
     ap.add_argument("--n-per-lambda", type=int, default=10_000_000)
-    ap.add_argument("--step-packets", type=int, default=500_000,
+    ap.add_argument("--step-packets", type=int, default=1_000_000,
                     help="packet ids per wavelength in one step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--threshold", type=int, default=0)
+    ap.add_argument("--brick", default="", help="log2 brick sizes, e.g. 1,0,4")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only print the memory-system microbenchmarks (one JSON line)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.microbench:
+        print(json.dumps(microbenchmarks()))
+        return
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is documented, not built)", file=sys.stderr)
@@ -134,8 +167,10 @@ def main():
     N = args.n_per_lambda
     B = min(args.step_packets, N)
     ctx = mcrt.Context(0)
+    brick = tuple(int(x) for x in args.brick.split(",")) if args.brick else None
     sim = mcrt.Sim(ctx, scene, mcrt.FP32, chunk=args.chunk or None,
-                   waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None)
+                   waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None,
+                   brick=brick)
     res = sim.new_result()
     nl = scene.n_lambda
     print(f"[bench] workload={args.workload} n_lambda={nl} step={B} ids/lambda "
@@ -178,6 +213,12 @@ def main():
         meta = json.load(open(prof))
         if meta.get("kernel_hash") == kernel_sources_hash():
             traffic = meta["hbm_bytes_per_packet"] * packets / args.steps
+    # the atomic-throughput ceiling measured on this device (random FP64 atomic
+    # adds over a working set the size of one wavelength slice of the table)
+    slice_bytes = 8 * scene.n_cells
+    atomic_ceiling = mcrt.microbench("atomic_f64", max(slice_bytes, 1 << 21), 1 << 28)
+    n_atomic = st["prop_cells"] * packets / max(st["packets"], 1)
+    atomics_per_s = n_atomic / args.steps / avg_kernel_s
     out = {
         "metric": METRIC,
         "value": packets / T,
@@ -196,6 +237,9 @@ def main():
                    "instruments": [list(i.npix) for i in scene.instruments]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "atomic_roofline": {"achieved": atomics_per_s, "peak": atomic_ceiling, "unit": "FP64 atomics/s",
+                            "frac": atomics_per_s / atomic_ceiling,
+                            "peak_kind": "measured random FP64 atomic adds, device scope"},
         "energy_balance": balance,
         "counters_per_packet": {f: st[f] / max(st["packets"], 1) for f in
                                 ("events", "prop_cells", "locate_cells", "peel_cells", "peel_adds")},

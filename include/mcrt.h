@@ -79,6 +79,9 @@ typedef struct {
     int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = default */
     int32_t threshold;     /* lanes that must finish a march before events run; 0 = default */
     int32_t top_level;     /* octree top-table level; -1 = default */
+    int32_t brick[3];      /* Cartesian storage bricks: log2 cells per axis, summing to 5
+                              (32 cells per brick); {-1, -1, -1} = chosen from the cell
+                              aspect ratio */
 } mcrt_options;
 
 typedef struct {
@@ -186,6 +189,19 @@ int mcrt_sim_info(const mcrt_sim *sim, int64_t *n_cells, int32_t *n_lambda, int3
 
 /* Thread-local message describing the last failure of this thread. */
 const char *mcrt_last_error(void);
+
+/* Memory-system microbenchmarks giving the transport kernel its roofline
+ * denominators (random access is what bounds the method: the paper's
+ * Section 1 calls Monte Carlo radiative transfer memory-bound with random
+ * access patterns).  kind: 0 random 4-byte gathers, 1 random FP64 atomic adds
+ * (device scope), 2 random FP64 atomic adds (workgroup scope), 3 random FP32
+ * atomic adds, 4 streaming copy, 5 FP64 atomic adds in runs of 4 consecutive
+ * elements.  bytes = working-set size (>= 4096), n_ops = operations.  *rate
+ * receives operations/s (bytes/s, read + written, for the copy).  Allocates
+ * and frees its own buffers; synchronises the device.  Errors: MCRT_EINVAL,
+ * MCRT_ENOMEM, MCRT_EDEVICE (message in mcrt_microbench_error()). */
+int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_ops, double *rate);
+const char *mcrt_microbench_error(void);
 
 #ifdef __cplusplus
 }

@@ -29,34 +29,54 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream)
     return hipGetLastError();
 }
 
-// dst[(c - cell0) * n_lambda + l] = src[l * n_cells + c] for c in [cell0, cell0 + ncell);
-// 64 x 64 tiles through LDS so both sides are coalesced.
-__global__ void table_transpose_kernel(const double *src, double *dst, int64_t n_cells, int n_lambda,
-                                       int64_t cell0, int64_t ncell)
+struct Layout {
+    int n[3], bs[3], nb[3];
+    int bricked;
+};
+
+__device__ __forceinline__ int64_t layout_store(const Layout &L, int64_t c)
 {
-    __shared__ double tile[64][65];
-    int64_t c_base = cell0 + (int64_t)blockIdx.x * 64;
-    int l_base = blockIdx.y * 64;
-    int tx = threadIdx.x & 63, ty = threadIdx.x >> 6; // 256 threads: 64 x 4
-    for (int r = ty; r < 64; r += 4) {
-        int l = l_base + r;
-        int64_t c = c_base + tx;
-        if (l < n_lambda && c < cell0 + ncell) tile[r][tx] = src[(int64_t)l * n_cells + c];
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        int64_t c = c_base + r;
-        int l = l_base + tx;
-        if (l < n_lambda && c < cell0 + ncell) dst[(c - cell0) * n_lambda + l] = tile[tx][r];
+    if (!L.bricked) return c;
+    int ix = (int)(c % L.n[0]);
+    int iy = (int)((c / L.n[0]) % L.n[1]);
+    int iz = (int)(c / ((int64_t)L.n[0] * L.n[1]));
+    int brick = (ix >> L.bs[0]) + L.nb[0] * ((iy >> L.bs[1]) + L.nb[1] * (iz >> L.bs[2]));
+    int in = (ix & ((1 << L.bs[0]) - 1)) + ((iy & ((1 << L.bs[1]) - 1)) << L.bs[0]) +
+             ((iz & ((1 << L.bs[2]) - 1)) << (L.bs[0] + L.bs[1]));
+    return (int64_t)brick * 32 + in;
+}
+
+// dst[(c - cell0) * n_lambda + l] = src[l * n_store + store(c)]: one thread per
+// (cell, wavelength) pair, wavelength fastest so the writes are coalesced.
+__global__ void table_readback_kernel(const double *src, double *dst, int64_t n_store, int n_lambda, Layout L,
+                                      int64_t cell0, int64_t ncell)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t total = ncell * n_lambda;
+    for (; i < total; i += stride) {
+        int64_t c = cell0 + i / n_lambda;
+        int l = (int)(i % n_lambda);
+        dst[i] = src[(int64_t)l * n_store + layout_store(L, c)];
     }
 }
 
-hipError_t launch_table_transpose(const double *src, double *dst, int64_t n_cells, int n_lambda,
-                                  int64_t cell0, int64_t ncell, hipStream_t stream)
+hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store, int n_lambda, const int *n,
+                                 const int *bs, const int *nb, int64_t cell0, int64_t ncell, hipStream_t stream)
 {
-    dim3 grid((unsigned)((ncell + 63) / 64), (unsigned)((n_lambda + 63) / 64));
-    hipLaunchKernelGGL(table_transpose_kernel, grid, dim3(256), 0, stream, src, dst, n_cells, n_lambda,
-                       cell0, ncell);
+    Layout L{};
+    L.bricked = bs != nullptr;
+    for (int a = 0; a < 3; ++a) {
+        L.n[a] = n ? n[a] : 1;
+        L.bs[a] = bs ? bs[a] : 0;
+        L.nb[a] = nb ? nb[a] : 1;
+    }
+    int64_t total = ncell * n_lambda;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(table_readback_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, src, dst, n_store,
+                       n_lambda, L, cell0, ncell);
     return hipGetLastError();
 }
 

@@ -10,12 +10,12 @@ namespace mcrt {
 constexpr int kBlock = 256;    // threads per workgroup (4 waves)
 constexpr int kNumStats = 9;   // packets, events, prop, locate, peel cells, adds, dropped, capped, guard
 
-template <typename Real, typename ImgT> struct View;
+template <typename Real, typename ImgT, int G> struct View;
 template <typename Real> struct Optics;
 template <typename Real> struct InsDesc;
 
-template <typename Real, typename ImgT> struct TransportArgs {
-    View<Real, ImgT> view;
+template <typename Real, typename ImgT, int G> struct TransportArgs {
+    View<Real, ImgT, G> view;
     const Optics<Real> *optics;   // global copies, staged into LDS by the kernel
     const InsDesc<Real> *ins;
     uint64_t total;               // packets in this launch: n_lambda * count
@@ -28,13 +28,20 @@ template <typename Real, typename ImgT> struct TransportArgs {
     unsigned long long *stats;    // [kNumStats]
 };
 
-hipError_t launch_transport_f32(const TransportArgs<float, float> &a, int grid, hipStream_t stream);
-hipError_t launch_transport_f64(const TransportArgs<double, double> &a, int grid, hipStream_t stream);
+// G = 0 Cartesian, 1 octree
+hipError_t launch_transport_f32c(const TransportArgs<float, float, 0> &a, int grid, hipStream_t stream);
+hipError_t launch_transport_f32o(const TransportArgs<float, float, 1> &a, int grid, hipStream_t stream);
+hipError_t launch_transport_f64c(const TransportArgs<double, double, 0> &a, int grid, hipStream_t stream);
+hipError_t launch_transport_f64o(const TransportArgs<double, double, 1> &a, int grid, hipStream_t stream);
 
 // auxiliary kernels (aux_kernels.hip)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
-hipError_t launch_table_transpose(const double *src, double *dst, int64_t n_cells, int n_lambda,
-                                  int64_t cell0, int64_t ncell, hipStream_t stream);
+// dst[(c - cell0) * n_lambda + l] = src[l * n_store + store(c)] for cells c in
+// [cell0, cell0 + ncell); store() is the bricked layout (bs, nb) of a
+// Cartesian grid with n cells per axis, or the identity when bs == NULL.
+hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store, int n_lambda,
+                                 const int *n, const int *bs, const int *nb, int64_t cell0,
+                                 int64_t ncell, hipStream_t stream);
 template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);
 

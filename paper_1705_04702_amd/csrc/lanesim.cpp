@@ -75,10 +75,10 @@ typedef struct {
 
 }
 
-template <typename Real>
+template <typename Real, int G>
 static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, uint64_t seed, ls_out *o)
 {
-    View<Real, Real> v{};
+    View<Real, Real, G> v{};
     std::vector<int32_t> node, top;
     int depth = 0;
     if (s->grid_type == kOctree) {
@@ -91,14 +91,30 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     } else {
         for (int a = 0; a < 3; ++a) v.n[a] = s->n[a];
     }
-    v.grid_type = s->grid_type;
     v.depth = depth;
     for (int a = 0; a < 3; ++a) {
         v.lo[a] = (Real)s->box[a];
         v.hi[a] = (Real)s->box[3 + a];
         v.cs[a] = (Real)((s->box[3 + a] - s->box[a]) / (double)v.n[a]);
     }
-    v.density = s->density;
+    std::vector<float> stored;
+    v.n_store = s->n_cells;
+    if (G == kCartesian) {
+        double cs[3];
+        for (int a = 0; a < 3; ++a) cs[a] = (s->box[3 + a] - s->box[a]) / (double)v.n[a];
+        long long ns;
+        choose_bricks(cs, v.n, v.bs, v.nb, ns);
+        v.n_store = ns;
+        stored.assign((size_t)ns, 0.0f);
+        for (int iz = 0; iz < v.n[2]; ++iz)
+            for (int iy = 0; iy < v.n[1]; ++iy)
+                for (int ix = 0; ix < v.n[0]; ++ix)
+                    stored[(size_t)store_index_host(v.bs, v.nb, ix, iy, iz)] =
+                        s->density[ix + (size_t)v.n[0] * (iy + (size_t)v.n[1] * iz)];
+        v.density = stored.data();
+    } else {
+        v.density = s->density;
+    }
     v.node = node.data();
     v.top = top.data();
     v.n_cells = s->n_cells;
@@ -122,7 +138,7 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         off += (long long)s->n_lambda * h.npix[0] * h.npix[1];
     }
     v.ins = ins.data();
-    std::vector<double> table((size_t)s->n_cells * s->n_lambda, 0.0);
+    std::vector<double> table((size_t)v.n_store * s->n_lambda, 0.0);
     std::vector<Real> images((size_t)(off > 0 ? off : 1), Real(0));
     v.table = table.data();
     v.images = images.data();
@@ -147,8 +163,14 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
             }
         }
     }
-    for (int64_t c = 0; c < s->n_cells; ++c)
-        for (int l = 0; l < s->n_lambda; ++l) o->table[c * s->n_lambda + l] = table[(size_t)l * s->n_cells + c];
+    for (int64_t c = 0; c < s->n_cells; ++c) {
+        long long sc = c;
+        if (G == kCartesian) {
+            int ix = (int)(c % v.n[0]), iy = (int)((c / v.n[0]) % v.n[1]), iz = (int)(c / ((int64_t)v.n[0] * v.n[1]));
+            sc = store_index_host(v.bs, v.nb, ix, iy, iz);
+        }
+        for (int l = 0; l < s->n_lambda; ++l) o->table[c * s->n_lambda + l] = table[(size_t)l * v.n_store + sc];
+    }
     for (int j = 0; j < s->n_ins; ++j) {
         long long n = (long long)s->n_lambda * s->ins_npix[2 * j] * s->ins_npix[2 * j + 1];
         for (long long q = 0; q < n; ++q) o->images[ins[j].offset + q] = (double)images[ins[j].offset + q] * inv4pid2[j];
@@ -167,6 +189,10 @@ extern "C" int ls_run(const ls_scene *s, uint64_t n_per_lambda, uint64_t first_i
                       ls_out *out)
 {
     if (!s || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
-    if (s->precision == 1) return run<double>(s, n_per_lambda, first_id, count, seed, out);
-    return run<float>(s, n_per_lambda, first_id, count, seed, out);
+    if (s->grid_type == kOctree) {
+        if (s->precision == 1) return run<double, kOctree>(s, n_per_lambda, first_id, count, seed, out);
+        return run<float, kOctree>(s, n_per_lambda, first_id, count, seed, out);
+    }
+    if (s->precision == 1) return run<double, kCartesian>(s, n_per_lambda, first_id, count, seed, out);
+    return run<float, kCartesian>(s, n_per_lambda, first_id, count, seed, out);
 }

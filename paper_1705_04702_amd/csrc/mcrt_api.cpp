@@ -118,6 +118,8 @@ struct mcrt_sim {
     long long image_elems = 0;
     mcrt_options opt{};
     int depth = 0, top_level = 0;
+    int bs[3] = {0, 0, 0}, nb[3] = {1, 1, 1}; // Cartesian brick layout
+    long long n_store = 0;                     // stored cells per wavelength slice
     // device copies of the scene
     float *d_density = nullptr;
     int *d_node = nullptr;
@@ -153,6 +155,7 @@ void mcrt_options_default(mcrt_options *opt)
     opt->waves_per_cu = 0;
     opt->threshold = 0;
     opt->top_level = -1;
+    opt->brick[0] = opt->brick[1] = opt->brick[2] = -1;
 }
 
 int mcrt_context_create(int device, void *stream, mcrt_context **out)
@@ -378,6 +381,10 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         return fail(MCRT_EINVAL, "sim_create: w_min >= 0, tau_peel_max > 0, event_cap >= 1 required");
     if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64)
         return fail(MCRT_EINVAL, "sim_create: tuning values out of range");
+    if (o.brick[0] >= 0 || o.brick[1] >= 0 || o.brick[2] >= 0) {
+        if (o.brick[0] < 0 || o.brick[1] < 0 || o.brick[2] < 0 || o.brick[0] + o.brick[1] + o.brick[2] != 5)
+            return fail(MCRT_EINVAL, "sim_create: brick log2 sizes must be >= 0 and sum to 5");
+    }
     HIP_TRY(hipSetDevice(ctx->device));
     auto *s = new mcrt_sim;
     s->ctx = ctx;
@@ -397,9 +404,36 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
     }
     s->image_elems = off;
     const mcrt_grid *g = medium->grid;
-    int rc = dev_alloc((void **)&s->d_density, (size_t)g->n_cells * sizeof(float));
+    std::vector<float> stored;
+    const float *dens = medium->density.data();
+    s->n_store = g->n_cells;
+    if (g->type == kCartesian) {
+        double cs[3];
+        for (int a = 0; a < 3; ++a) cs[a] = (g->box[3 + a] - g->box[a]) / (double)g->n[a];
+        choose_bricks(cs, g->n, s->bs, s->nb, s->n_store);
+        if (o.brick[0] >= 0) {
+            s->n_store = 32;
+            for (int a = 0; a < 3; ++a) {
+                s->bs[a] = o.brick[a];
+                s->nb[a] = (g->n[a] + (1 << s->bs[a]) - 1) >> s->bs[a];
+                s->n_store *= s->nb[a];
+            }
+        }
+        if (s->n_store >= (1ll << 31)) {
+            delete s;
+            return fail(MCRT_EINVAL, "sim_create: bricked grid exceeds 2^31 cells");
+        }
+        stored.assign((size_t)s->n_store, 0.0f);
+        for (int iz = 0; iz < g->n[2]; ++iz)
+            for (int iy = 0; iy < g->n[1]; ++iy)
+                for (int ix = 0; ix < g->n[0]; ++ix)
+                    stored[(size_t)store_index_host(s->bs, s->nb, ix, iy, iz)] =
+                        dens[ix + (size_t)g->n[0] * (iy + (size_t)g->n[1] * iz)];
+        dens = stored.data();
+    }
+    int rc = dev_alloc((void **)&s->d_density, (size_t)s->n_store * sizeof(float));
     if (!rc) {
-        hipError_t e = hipMemcpy(s->d_density, medium->density.data(), (size_t)g->n_cells * sizeof(float), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(s->d_density, dens, (size_t)s->n_store * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("density upload: ") + hipGetErrorString(e));
     }
     if (!rc && g->type == kOctree) {
@@ -441,7 +475,7 @@ static size_t image_bytes(const mcrt_sim *s)
     return (size_t)s->image_elems * (s->opt.precision == MCRT_FP32 ? sizeof(float) : sizeof(double));
 }
 
-static size_t table_elems(const mcrt_sim *s) { return (size_t)s->medium->grid->n_cells * (size_t)s->medium->n_lambda; }
+static size_t table_elems(const mcrt_sim *s) { return (size_t)s->n_store * (size_t)s->medium->n_lambda; }
 
 void mcrt_result_destroy(mcrt_result *res)
 {
@@ -494,7 +528,7 @@ int mcrt_result_create(mcrt_sim *sim, mcrt_result **out)
     return MCRT_OK;
 }
 
-template <typename Real, typename ImgT>
+template <typename Real, typename ImgT, int G>
 static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
                     mcrt_result *r)
 {
@@ -511,10 +545,11 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_zero(r->d_counter, sizeof(unsigned long long), st));
 
-    TransportArgs<Real, ImgT> a{};
-    View<Real, ImgT> &v = a.view;
-    v.grid_type = g->type;
+    TransportArgs<Real, ImgT, G> a{};
+    View<Real, ImgT, G> &v = a.view;
     for (int c = 0; c < 3; ++c) {
+        v.bs[c] = s->bs[c];
+        v.nb[c] = s->nb[c];
         v.n[c] = g->n[c];
         v.lo[c] = (Real)g->box[c];
         v.hi[c] = (Real)g->box[3 + c];
@@ -526,6 +561,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     v.node = s->d_node;
     v.top = s->d_top;
     v.n_cells = g->n_cells;
+    v.n_store = s->n_store;
     v.n_lambda = m->n_lambda;
     v.optics = nullptr;
     v.src_type = s->source->type;
@@ -565,8 +601,10 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le;
-    if constexpr (sizeof(Real) == 4) le = launch_transport_f32(a, grid, st);
-    else le = launch_transport_f64(a, grid, st);
+    if constexpr (sizeof(Real) == 4 && G == kCartesian) le = launch_transport_f32c(a, grid, st);
+    else if constexpr (sizeof(Real) == 4) le = launch_transport_f32o(a, grid, st);
+    else if constexpr (G == kCartesian) le = launch_transport_f64c(a, grid, st);
+    else le = launch_transport_f64o(a, grid, st);
     HIP_TRY(le);
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
@@ -610,8 +648,13 @@ int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint6
     if (!guard.owned) return fail(MCRT_EBUSY, "run_into: the simulation is already running");
     if (count == 0) return MCRT_OK;
     HIP_TRY(hipSetDevice(sim->ctx->device));
-    if (sim->opt.precision == MCRT_FP32) return run_impl<float, float>(sim, n_per_lambda, first_id, count, seed, res);
-    return run_impl<double, double>(sim, n_per_lambda, first_id, count, seed, res);
+    const bool oct = sim->medium->grid->type == kOctree;
+    if (sim->opt.precision == MCRT_FP32) {
+        if (oct) return run_impl<float, float, kOctree>(sim, n_per_lambda, first_id, count, seed, res);
+        return run_impl<float, float, kCartesian>(sim, n_per_lambda, first_id, count, seed, res);
+    }
+    if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res);
+    return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res);
 }
 
 int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
@@ -642,9 +685,11 @@ int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count)
 {
     if (!res || !out) return fail(MCRT_EINVAL, "result_absorption: NULL argument");
     const mcrt_sim *s = res->sim;
-    const int64_t nc = s->medium->grid->n_cells;
+    const mcrt_grid *g = s->medium->grid;
+    const int64_t nc = g->n_cells;
     const int nl = s->medium->n_lambda;
-    if (count < table_elems(s)) return fail(MCRT_EINVAL, "result_absorption: output buffer too small");
+    if (count < (size_t)nc * (size_t)nl) return fail(MCRT_EINVAL, "result_absorption: output buffer too small");
+    const bool bricked = g->type == kCartesian;
     HIP_TRY(hipSetDevice(s->ctx->device));
     hipStream_t st = s->ctx->stream;
     int64_t block = std::max<int64_t>(1, ((int64_t)1 << 25) / nl); // cells per pass (<= 256 MB)
@@ -654,7 +699,8 @@ int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count)
     if (rc) return rc;
     for (int64_t c0 = 0; c0 < nc; c0 += block) {
         int64_t n = std::min(block, nc - c0);
-        hipError_t e = launch_table_transpose(res->d_table, tmp, nc, nl, c0, n, st);
+        hipError_t e = launch_table_readback(res->d_table, tmp, s->n_store, nl, g->n, bricked ? s->bs : nullptr,
+                                             s->nb, c0, n, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(out + c0 * nl, tmp, (size_t)n * nl * sizeof(double), hipMemcpyDefault, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -121,4 +121,46 @@ inline void build_top_table(const std::vector<int32_t> &node, int top_level, std
             }
 }
 
+// Brick shape for the Cartesian storage layout: 32 cells per brick (one
+// 128-byte line of FP32 densities): runs of up to 16 cells along x (the
+// grid's fastest axis), the remaining doublings on the axis whose brick is
+// physically shortest, never beyond the grid's own extent (rounded up to a
+// power of two).  Returns log2 sizes in bs and bricks per axis in nb.
+inline void choose_bricks(const double cs[3], const int n[3], int bs[3], int nb[3], long long &n_store)
+{
+    int lim[3];
+    for (int a = 0; a < 3; ++a) {
+        bs[a] = 0;
+        lim[a] = 0;
+        while ((1 << lim[a]) < n[a]) lim[a]++;
+    }
+    bs[0] = lim[0] < 4 ? lim[0] : 4;
+    for (int k = bs[0]; k < 5; ++k) {
+        int best = -1;
+        double ext = 0.0;
+        for (int a = 1; a < 3; ++a) {
+            double e = cs[a] * (double)(1 << bs[a]);
+            if (bs[a] < lim[a] && (best < 0 || e < ext)) {
+                best = a;
+                ext = e;
+            }
+        }
+        if (best < 0) best = 0; // grid smaller than a brick: pad along x
+        bs[best]++;
+    }
+    n_store = 32;
+    for (int a = 0; a < 3; ++a) {
+        nb[a] = (n[a] + (1 << bs[a]) - 1) >> bs[a];
+        n_store *= nb[a];
+    }
+}
+
+inline long long store_index_host(const int bs[3], const int nb[3], int ix, int iy, int iz)
+{
+    long long brick = (ix >> bs[0]) + (long long)nb[0] * ((iy >> bs[1]) + (long long)nb[1] * (iz >> bs[2]));
+    int in = (ix & ((1 << bs[0]) - 1)) + ((iy & ((1 << bs[1]) - 1)) << bs[0]) +
+             ((iz & ((1 << bs[2]) - 1)) << (bs[0] + bs[1]));
+    return brick * 32 + in;
+}
+
 } // namespace mcrt

@@ -30,6 +30,7 @@ enum Mode : int {
     kProp = 2,      // propagation march with continuous absorption
     kLocate = 3,    // second march to the forced interaction point
     kPeelScat = 4,  // scattering peel-off march towards instrument j
+    kLaunched = 5,  // launched, first march not yet begun
 };
 
 enum GridType : int { kCartesian = 0, kOctree = 1 };
@@ -109,9 +110,8 @@ template <typename Real> struct Optics {
     Real kappa, albedo, g, L0;
 };
 
-template <typename Real, typename ImgT> struct View {
+template <typename Real, typename ImgT, int G> struct View {
     // grid
-    int grid_type;
     int n[3];       // cells per axis (Cartesian) or lattice size 2^depth (octree)
     int depth;      // octree maximum depth
     int top_level;  // octree: level of the dense top table
@@ -120,6 +120,10 @@ template <typename Real, typename ImgT> struct View {
     const int *node;     // octree: >= 0 first child, < 0 -(leaf + 1)
     const int *top;      // octree: (level << 27) | node for each top-table block
     long long n_cells;
+    // Cartesian storage layout: bricks of 2^bs[0] x 2^bs[1] x 2^bs[2] = 32 cells,
+    // nb[] bricks per axis; n_store = cells per wavelength slice incl. padding
+    int bs[3], nb[3];
+    long long n_store;
     // per wavelength
     int n_lambda;
     const Optics<Real> *optics;
@@ -131,7 +135,7 @@ template <typename Real, typename ImgT> struct View {
     int n_ins;
     const InsDesc<Real> *ins;
     // outputs
-    double *table;  // [n_lambda][n_cells]
+    double *table;  // [n_lambda][n_store]
     ImgT *images;   // [n_ins][n_lambda][ny][nx], flux * 4 pi d^2
     // options
     Real w_min;
@@ -150,19 +154,26 @@ struct Tally {
 template <typename Real> struct Lane {
     Real r[3], k[3];    // packet position and direction
     Real d[3], id3[3];  // march direction and its reciprocal
-    Real tn[3];         // Cartesian: ray parameter of the next plane per axis
+    Real tn0, tn1, tn2; // Cartesian: ray parameter of the next plane per axis
     Real t;             // ray parameter at the start of the current segment
     Real L, L0;         // current luminosity, launch luminosity
     Real wpeel;         // peel-off luminosity times phase
     Real E, tau, wabs, tau_int;
     Real a_t0, a_tau, a_kr, a_ds; // locate: last segment with positive optical depth
     Optics<Real> opt;
-    int ci[3];          // cell index (Cartesian) or lattice cursor (octree)
+    int c0, c1, c2;     // cell index (Cartesian) or lattice cursor (octree)
     int mode, j, nseg, steps;
     long long e;
     uint32_t id, lam;
     bool marching, found, dropped;
 };
+
+// Per-axis fields are separate scalars (not arrays): stores through a
+// runtime axis index would move the lane state to scratch memory.  These
+// accessors are only called with compile-time axis numbers.
+template <typename Real> MCRT_HD int &cidx(Lane<Real> &ln, int a) { return a == 0 ? ln.c0 : (a == 1 ? ln.c1 : ln.c2); }
+template <typename Real> MCRT_HD int cidx(const Lane<Real> &ln, int a) { return a == 0 ? ln.c0 : (a == 1 ? ln.c1 : ln.c2); }
+template <typename Real> MCRT_HD Real &tnx(Lane<Real> &ln, int a) { return a == 0 ? ln.tn0 : (a == 1 ? ln.tn1 : ln.tn2); }
 
 // ---------------------------------------------------------------------------
 // Precision traits: FP64 divides exactly like the reference; FP32 multiplies
@@ -179,6 +190,18 @@ template <> struct Prec<double> {
 };
 
 template <typename Real> MCRT_HD Real rmax(Real a, Real b) { return a > b ? a : b; }
+
+// Storage position of Cartesian cell (ix, iy, iz): bricks of 32 cells shaped
+// to the cells' aspect ratio, so that successive cells of a ray tend to share
+// cache lines of the density and table arrays.
+template <typename Real, typename ImgT, int G>
+MCRT_HD int store_index(const View<Real, ImgT, G> &v, int ix, int iy, int iz)
+{
+    int brick = (ix >> v.bs[0]) + v.nb[0] * ((iy >> v.bs[1]) + v.nb[1] * (iz >> v.bs[2]));
+    int in = (ix & ((1 << v.bs[0]) - 1)) + ((iy & ((1 << v.bs[1]) - 1)) << v.bs[0]) +
+             ((iz & ((1 << v.bs[2]) - 1)) << (v.bs[0] + v.bs[1]));
+    return brick * 32 + in;
+}
 
 // Elementary functions: the device math library in FP32; in FP64 the
 // fixed-sequence implementations of det_math.h.
@@ -218,8 +241,8 @@ template <typename Real> MCRT_HD int slice_index(Real p, Real lo, Real cs, int n
 }
 
 // Start of the ray r + t d (t >= 0) in the grid box: t0 and slice indices.
-template <typename Real, typename ImgT>
-MCRT_HD bool ray_start(const View<Real, ImgT> &v, const Real r[3], const Real d[3], Real &t0, int idx[3])
+template <typename Real, typename ImgT, int G>
+MCRT_HD bool ray_start(const View<Real, ImgT, G> &v, const Real r[3], const Real d[3], Real &t0, int idx[3])
 {
     bool inside = true;
 #pragma unroll
@@ -266,23 +289,23 @@ MCRT_HD bool ray_start(const View<Real, ImgT> &v, const Real r[3], const Real d[
     return true;
 }
 
-template <typename Real, typename ImgT>
-MCRT_HD Real plane_t(const View<Real, ImgT> &v, const Lane<Real> &ln, int a, int j)
+template <typename Real, typename ImgT, int G>
+MCRT_HD Real plane_t(const View<Real, ImgT, G> &v, const Lane<Real> &ln, int a, int j)
 {
     return Prec<Real>::over_k(v.lo[a] + (Real)j * v.cs[a] - ln.r[a], ln.d[a], ln.id3[a]);
 }
 
-template <typename Real, typename ImgT>
-MCRT_HD Real next_plane_t(const View<Real, ImgT> &v, const Lane<Real> &ln, int a)
+template <typename Real, typename ImgT, int G>
+MCRT_HD Real next_plane_t(const View<Real, ImgT, G> &v, const Lane<Real> &ln, int a)
 {
-    if (ln.d[a] > Real(0)) return plane_t(v, ln, a, ln.ci[a] + 1);
-    if (ln.d[a] < Real(0)) return plane_t(v, ln, a, ln.ci[a]);
+    if (ln.d[a] > Real(0)) return plane_t(v, ln, a, cidx(ln, a) + 1);
+    if (ln.d[a] < Real(0)) return plane_t(v, ln, a, cidx(ln, a));
     return Prec<Real>::inf();
 }
 
 // Begins a march from the packet position along direction dir.
-template <typename Real, typename ImgT>
-MCRT_HD void begin_march(const View<Real, ImgT> &v, Lane<Real> &ln, const Real dir[3])
+template <typename Real, typename ImgT, int G>
+MCRT_HD void begin_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, const Real dir[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -293,11 +316,18 @@ MCRT_HD void begin_march(const View<Real, ImgT> &v, Lane<Real> &ln, const Real d
     ln.steps = 0;
     ln.tau = Real(0);
     Real t0;
-    ln.marching = ray_start(v, ln.r, ln.d, t0, ln.ci);
+    int idx[3];
+    ln.marching = ray_start(v, ln.r, ln.d, t0, idx);
+    ln.c0 = idx[0];
+    ln.c1 = idx[1];
+    ln.c2 = idx[2];
     ln.t = t0;
-    if (ln.marching && v.grid_type == kCartesian) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ln.tn[a] = next_plane_t(v, ln, a);
+    if constexpr (G == kCartesian) {
+        if (ln.marching) {
+            ln.tn0 = next_plane_t(v, ln, 0);
+            ln.tn1 = next_plane_t(v, ln, 1);
+            ln.tn2 = next_plane_t(v, ln, 2);
+        }
     }
 }
 
@@ -305,46 +335,53 @@ MCRT_HD void begin_march(const View<Real, ImgT> &v, Lane<Real> &ln, const Real d
 // One segment of the march: finds the cell and its path length, then applies
 // the mode's action (deposit, optical-depth sum, interaction search).
 // ---------------------------------------------------------------------------
-template <typename Real, typename ImgT, typename Sink>
-MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+// One geometric step of the march: the cell the ray is in, where it leaves
+// it, and the lattice state advanced to the next cell.  Needs no density, so
+// several steps can be taken before their density loads complete.  Returns
+// true when the ray leaves the grid after this segment.
+template <typename Real, typename ImgT, int G>
+MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, int &cell, Real &te)
 {
-    // All per-axis arrays are indexed with compile-time constants (unrolled
-    // loops with `a == am` tests) so that the lane state stays in registers.
-    int cell;
-    Real te;
     bool exits = false;
-    if (v.grid_type == kCartesian) {
-        Real tmin = ln.tn[0];
+    if constexpr (G == kCartesian) {
+        Real tmin = ln.tn0;
         int am = 0;
-        if (ln.tn[1] < tmin) {
-            tmin = ln.tn[1];
+        if (ln.tn1 < tmin) {
+            tmin = ln.tn1;
             am = 1;
         }
-        if (ln.tn[2] < tmin) {
-            tmin = ln.tn[2];
+        if (ln.tn2 < tmin) {
+            tmin = ln.tn2;
             am = 2;
         }
         te = rmax(tmin, ln.t);
-        cell = ln.ci[0] + v.n[0] * (ln.ci[1] + v.n[1] * ln.ci[2]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a == am) {
-                ln.ci[a] += ln.d[a] > Real(0) ? 1 : -1;
-                exits = ln.ci[a] < 0 || ln.ci[a] >= v.n[a];
-                if (!exits) ln.tn[a] = next_plane_t(v, ln, a);
-            }
+        cell = store_index(v, ln.c0, ln.c1, ln.c2);
+        // explicit per-axis branches (a loop over `a == am` gets folded into a
+        // runtime-indexed store, which would move the arrays to scratch)
+        if (am == 0) {
+            ln.c0 += ln.d[0] > Real(0) ? 1 : -1;
+            exits = ln.c0 < 0 || ln.c0 >= v.n[0];
+            if (!exits) ln.tn0 = next_plane_t(v, ln, 0);
+        } else if (am == 1) {
+            ln.c1 += ln.d[1] > Real(0) ? 1 : -1;
+            exits = ln.c1 < 0 || ln.c1 >= v.n[1];
+            if (!exits) ln.tn1 = next_plane_t(v, ln, 1);
+        } else {
+            ln.c2 += ln.d[2] > Real(0) ? 1 : -1;
+            exits = ln.c2 < 0 || ln.c2 >= v.n[2];
+            if (!exits) ln.tn2 = next_plane_t(v, ln, 2);
         }
     } else {
         // locate the leaf holding lattice point ci: dense top table, then descend
         const int sh = v.depth - v.top_level;
         const int T = 1 << v.top_level;
-        int packed = v.top[((ln.ci[2] >> sh) * T + (ln.ci[1] >> sh)) * T + (ln.ci[0] >> sh)];
+        int packed = v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
         int level = packed >> 27;
         int nd = packed & ((1 << 27) - 1);
         int val = v.node[nd];
         while (val >= 0) {
             int bit = v.depth - 1 - level;
-            int child = ((ln.ci[0] >> bit) & 1) + 2 * ((ln.ci[1] >> bit) & 1) + 4 * ((ln.ci[2] >> bit) & 1);
+            int child = ((ln.c0 >> bit) & 1) + 2 * ((ln.c1 >> bit) & 1) + 4 * ((ln.c2 >> bit) & 1);
             nd = val + child;
             val = v.node[nd];
             level++;
@@ -355,7 +392,7 @@ MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Si
         Real tn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            o[a] = ln.ci[a] & ~(size - 1);
+            o[a] = cidx(ln, a) & ~(size - 1);
             if (ln.d[a] > Real(0)) tn[a] = plane_t(v, ln, a, o[a] + size);
             else if (ln.d[a] < Real(0)) tn[a] = plane_t(v, ln, a, o[a]);
             else tn[a] = Prec<Real>::inf();
@@ -376,7 +413,7 @@ MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Si
             if (a == am) {
                 int q = ln.d[a] > Real(0) ? o[a] + size : o[a] - 1;
                 exits = q < 0 || q >= v.n[a];
-                ln.ci[a] = q;
+                cidx(ln, a) = q;
             } else {
                 Real p = ln.r[a] + te * ln.d[a];
                 Real qf = floor((p - v.lo[a]) / v.cs[a]);
@@ -384,7 +421,7 @@ MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Si
                 if (qf < Real(o[a])) qi = o[a];
                 else if (qf > Real(o[a] + size - 1)) qi = o[a] + size - 1;
                 else qi = (int)qf;
-                ln.ci[a] = qi;
+                cidx(ln, a) = qi;
             }
         }
         if (++ln.steps >= v.octree_guard) {
@@ -392,21 +429,30 @@ MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Si
             ty.guard++;
         }
     }
-    const Real ds = te - ln.t;
-    const Real t_start = ln.t;
-    ln.t = te;
+    return exits;
+}
+
+// Applies one segment (cell, start, length, density) to the lane's march:
+// continuous-absorption deposit, interaction search or optical-depth sum.
+// Returns true when the march stops here (interaction found, peel-off cut).
+template <typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD bool apply_segment(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink, int cell,
+                           Real t_start, Real ds, float rho)
+{
     ln.nseg++;
-    const Real kr = ln.opt.kappa * (Real)v.density[cell];
+    const Real kr = ln.opt.kappa * (Real)rho;
     const Real dtau = kr * ds;
     if (ln.mode == kProp) {
         Real x = -Math<Real>::e_expm1(-dtau);
         Real A = ln.wabs * ln.E * x;
-        sink.deposit(v.table + (long long)ln.lam * v.n_cells + cell, (double)A);
+        sink.deposit(v.table + (long long)ln.lam * v.n_store + cell, (double)A);
         ty.absorbed += (double)A;
         ln.E = ln.E * (Real(1) - x);
         ln.tau = ln.tau + dtau;
         ty.prop_cells++;
-    } else if (ln.mode == kLocate) {
+        return false;
+    }
+    if (ln.mode == kLocate) {
         ty.locate_cells++;
         Real tprev = ln.tau;
         ln.tau = ln.tau + dtau;
@@ -418,17 +464,63 @@ MCRT_HD void march_step(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Si
         }
         if (ln.tau >= ln.tau_int) {
             ln.found = true;
-            exits = true;
+            return true;
         }
-    } else {
-        ln.tau = ln.tau + dtau;
-        ty.peel_cells++;
-        if (ln.tau >= v.tau_peel_max) {
-            ln.dropped = true;
-            exits = true;
+        return false;
+    }
+    ln.tau = ln.tau + dtau;
+    ty.peel_cells++;
+    if (ln.tau >= v.tau_peel_max) {
+        ln.dropped = true;
+        return true;
+    }
+    return false;
+}
+
+// K segments of the march: K geometric steps, then K independent density
+// loads in flight together, then the segments applied in order (the same
+// operations in the same order as one segment at a time).
+template <int K, typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD void march_batch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    int cell[K];
+    Real ts[K], ds[K];
+    bool ok[K];
+    bool more = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        ok[k] = more;
+        cell[k] = 0;
+        ts[k] = ln.t;
+        ds[k] = Real(0);
+        if (more) {
+            Real te;
+            bool exits = geo_step(v, ln, ty, cell[k], te);
+            ds[k] = te - ln.t;
+            ln.t = te;
+            more = !exits;
         }
     }
-    if (exits) ln.marching = false;
+    float rho[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) rho[k] = ok[k] ? v.density[cell[k]] : 0.0f;
+    bool stop = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (ok[k] && !stop) stop = apply_segment(v, ln, ty, sink, cell[k], ts[k], ds[k], rho[k]);
+    if (stop || !more) ln.marching = false;
+}
+
+// Segments per march iteration: the Cartesian step is pure arithmetic, so
+// four loads can be put in flight; the octree step itself reads the tree.
+template <int G> struct BatchOf {
+    static constexpr int value = G == kCartesian ? 4 : 2;
+};
+
+template <typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD void march_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    march_batch<BatchOf<G>::value>(v, ln, ty, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -491,14 +583,14 @@ template <typename Real> struct Consts {
     MCRT_HD static Real two_pi() { return Real(6.283185307179586476925286766559); }
 };
 
-template <typename Real, typename ImgT>
-MCRT_HD Stream stream_of(const View<Real, ImgT> &v, const Lane<Real> &ln)
+template <typename Real, typename ImgT, int G>
+MCRT_HD Stream stream_of(const View<Real, ImgT, G> &v, const Lane<Real> &ln)
 {
     return Stream{v.key0, v.key1, ln.id, ln.lam, v.model};
 }
 
-template <typename Real, typename ImgT>
-MCRT_HD void begin_peel(const View<Real, ImgT> &v, Lane<Real> &ln, int j, bool emission)
+template <typename Real, typename ImgT, int G>
+MCRT_HD void begin_peel(const View<Real, ImgT, G> &v, Lane<Real> &ln, int j, bool emission)
 {
     ln.mode = emission ? kPeelEmit : kPeelScat;
     ln.j = j;
@@ -516,8 +608,8 @@ MCRT_HD void begin_peel(const View<Real, ImgT> &v, Lane<Real> &ln, int j, bool e
     begin_march(v, ln, in.kobs);
 }
 
-template <typename Real, typename ImgT>
-MCRT_HD void begin_prop(const View<Real, ImgT> &v, Lane<Real> &ln)
+template <typename Real, typename ImgT, int G>
+MCRT_HD void begin_prop(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
     ln.mode = kProp;
     ln.wabs = (Real(1) - ln.opt.albedo) * ln.L;
@@ -525,8 +617,8 @@ MCRT_HD void begin_prop(const View<Real, ImgT> &v, Lane<Real> &ln)
     begin_march(v, ln, ln.k);
 }
 
-template <typename Real, typename ImgT>
-MCRT_HD void begin_locate(const View<Real, ImgT> &v, Lane<Real> &ln)
+template <typename Real, typename ImgT, int G>
+MCRT_HD void begin_locate(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
     ln.mode = kLocate;
     ln.found = false;
@@ -534,8 +626,8 @@ MCRT_HD void begin_locate(const View<Real, ImgT> &v, Lane<Real> &ln)
 }
 
 // Scattering: new HG direction, then the next propagation (or the event cap).
-template <typename Real, typename ImgT>
-MCRT_HD void scatter(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty)
+template <typename Real, typename ImgT, int G>
+MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 {
     Stream st = stream_of(v, ln);
     Real u1 = st.template slot<Real>((uint32_t)(8 * ln.e + 1));
@@ -555,8 +647,8 @@ MCRT_HD void scatter(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty)
 }
 
 // Launches packet (lam, id): position, direction, emission peel-offs.
-template <typename Real, typename ImgT>
-MCRT_HD void launch(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id)
+template <typename Real, typename ImgT, int G>
+MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id)
 {
     ln.lam = lam;
     ln.id = id;
@@ -597,14 +689,19 @@ MCRT_HD void launch(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, uint32
     ln.e = 1;
     ty.emitted += (double)ln.L0;
     ty.packets++;
-    if (v.n_ins > 0) begin_peel(v, ln, 0, true);
-    else begin_prop(v, ln);
+    ln.mode = kLaunched;
+    ln.marching = false;
 }
 
 // Handles the end of a march; leaves the lane marching again or dead.
-template <typename Real, typename ImgT, typename Sink>
-MCRT_HD void finish_march(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+template <typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
+    if (ln.mode == kLaunched) {
+        if (v.n_ins > 0) begin_peel(v, ln, 0, true);
+        else begin_prop(v, ln);
+        return;
+    }
     if (ln.mode == kPeelEmit || ln.mode == kPeelScat) {
         const InsDesc<Real> &in = v.ins[ln.j];
         if (ln.dropped) {
@@ -667,8 +764,8 @@ MCRT_HD void finish_march(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, 
     ln.mode = kDead;
 }
 
-template <typename Real, typename ImgT, typename Sink>
-MCRT_HD void settle(const View<Real, ImgT> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+template <typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD void settle(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
     while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
 }

@@ -1,10 +1,14 @@
-// FP32 production instantiation: packet transport in single precision, FP64
-// table totals and energy sums.
+// FP32 production instantiations: packet transport in single precision, FP64
+// table totals and energy sums; one kernel per grid type.
 #include "transport_kernel.h"
 
 namespace mcrt {
-hipError_t launch_transport_f32(const TransportArgs<float, float> &a, int grid, hipStream_t stream)
+hipError_t launch_transport_f32c(const TransportArgs<float, float, 0> &a, int grid, hipStream_t stream)
 {
-    return launch_transport_impl<float, float>(a, grid, stream);
+    return launch_transport_impl<float, float, 0>(a, grid, stream);
+}
+hipError_t launch_transport_f32o(const TransportArgs<float, float, 1> &a, int grid, hipStream_t stream)
+{
+    return launch_transport_impl<float, float, 1>(a, grid, stream);
 }
 } // namespace mcrt

@@ -53,12 +53,12 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
-template <typename Real, typename ImgT>
-__global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, ImgT> a)
+template <typename Real, typename ImgT, int G>
+__global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, ImgT, G> a)
 {
     __shared__ Optics<Real> s_opt[kMaxLdsLambda];
     __shared__ InsDesc<Real> s_ins[kMaxIns];
-    View<Real, ImgT> v = a.view;
+    View<Real, ImgT, G> v = a.view;
     if (v.n_lambda <= kMaxLdsLambda) {
         for (int i = threadIdx.x; i < v.n_lambda; i += blockDim.x) s_opt[i] = a.optics[i];
         v.optics = s_opt;
@@ -79,9 +79,11 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
     bool exhausted = false;
 
     for (;;) {
-        // refill dead lanes from the wave's chunk (one atomic per chunk)
+        // refill dead lanes from the wave's chunk (one atomic per chunk); a
+        // refilled lane only launches here, its events run below
+        bool launched = false;
         for (;;) {
-            unsigned long long dead = __ballot(ln.mode == kDead);
+            unsigned long long dead = __ballot(ln.mode == kDead && !launched);
             if (dead == 0 || exhausted) break;
             if (cur >= end) {
                 unsigned long long c = 0;
@@ -98,17 +100,22 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
             }
             uint64_t avail = end - cur;
             uint32_t rank = lanes_below(dead);
-            if (ln.mode == kDead && (uint64_t)rank < avail) {
+            if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
                 uint32_t lam = (uint32_t)(P / a.count);
                 uint32_t id = (uint32_t)(a.first_id + P % a.count);
                 launch(v, ln, ty, lam, id);
-                settle(v, ln, ty, sink);
+                launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);
             cur += ndead < avail ? ndead : avail;
         }
-        if (__ballot(ln.mode != kDead) == 0) break;
+        // events of the lanes whose march ended (or that just launched)
+        if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
+        if (__ballot(ln.mode != kDead) == 0) {
+            if (exhausted) break;
+            continue;
+        }
 
         // march: every marching lane advances one cell per iteration
         for (;;) {
@@ -117,8 +124,6 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;
         }
-        // events of the lanes whose march ended
-        if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
     }
 
     double e0 = wave_sum(ty.emitted), e1 = wave_sum(ty.absorbed);
@@ -139,10 +144,10 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
     }
 }
 
-template <typename Real, typename ImgT>
-hipError_t launch_transport_impl(const TransportArgs<Real, ImgT> &a, int grid, hipStream_t stream)
+template <typename Real, typename ImgT, int G>
+hipError_t launch_transport_impl(const TransportArgs<Real, ImgT, G> &a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((transport_kernel<Real, ImgT>), dim3(grid), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((transport_kernel<Real, ImgT, G>), dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

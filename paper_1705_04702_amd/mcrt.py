@@ -16,7 +16,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmcrt.so")
+# MCRT_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MCRT_LIBRARY") or os.path.join(HERE, "libmcrt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ELIMIT = 0, -1, -2, -3, -4, -5
 FP32, FP64_VALIDATE = 0, 1
@@ -29,7 +30,7 @@ EXPORTS = [
     "mcrt_instrument_destroy", "mcrt_sim_create", "mcrt_sim_destroy", "mcrt_result_create",
     "mcrt_result_zero", "mcrt_run_into", "mcrt_run", "mcrt_run_range", "mcrt_result_absorption",
     "mcrt_result_image", "mcrt_result_energy", "mcrt_result_stats", "mcrt_result_destroy",
-    "mcrt_sim_info", "mcrt_last_error",
+    "mcrt_sim_info", "mcrt_last_error", "mcrt_microbench", "mcrt_microbench_error",
 ]
 
 
@@ -49,6 +50,7 @@ class Options(ctypes.Structure):
         ("waves_per_cu", ctypes.c_int32),
         ("threshold", ctypes.c_int32),
         ("top_level", ctypes.c_int32),
+        ("brick", ctypes.c_int32 * 3),
     ]
 
 
@@ -111,6 +113,9 @@ def lib():
         "mcrt_sim_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "mcrt_last_error": (ctypes.c_char_p, []),
+        "mcrt_microbench": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_double)]),
+        "mcrt_microbench_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -130,11 +135,29 @@ def _dptr(a):
     return a.ctypes.data_as(DP)
 
 
+MICROBENCH_KINDS = {"gather4": 0, "atomic_f64": 1, "atomic_f64_wg": 2, "atomic_f32": 3, "copy": 4,
+                    "atomic_f64_run4": 5}
+
+
+def microbench(kind: str, nbytes: int, n_ops: int = 1 << 28, device: int = 0) -> float:
+    """Operations/s (bytes/s for "copy") of a memory-system microbenchmark."""
+    r = ctypes.c_double()
+    rc = lib().mcrt_microbench(int(device), MICROBENCH_KINDS[kind], int(nbytes), int(n_ops), ctypes.byref(r))
+    if rc != OK:
+        raise MCRTError(rc, lib().mcrt_microbench_error().decode())
+    return r.value
+
+
 def default_options(**kw) -> Options:
     o = Options()
     lib().mcrt_options_default(ctypes.byref(o))
     for k, val in kw.items():
-        if val is not None:
+        if val is None:
+            continue
+        if k == "brick":
+            for a in range(3):
+                o.brick[a] = int(val[a])
+        else:
             setattr(o, k, val)
     return o
 

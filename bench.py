@@ -40,7 +40,7 @@ def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_04702_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.startswith("transport"):
+        if f.startswith("transport") or f in ("internal.h", "det_math.h"):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -171,6 +171,40 @@ int mcrt_run(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t seed, mcrt_result **
 int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
                    uint64_t seed, mcrt_result **out);
 
+/* Batched run (the many-small-models use case of Section 3.1): sims[i]
+ * (distinct Cartesian sims of one context and one precision) runs packet ids
+ * [0, n_per_lambda[i]) of each of its wavelengths and adds them to
+ * results[i] (created with mcrt_result_create for sims[i]), all in ONE
+ * persistent launch.  The position i in the batch is the fourth word of the
+ * packets' Philox counters, so results equal per-model runs with model = i.
+ * Queue tuning (chunk, threshold, waves per CU) comes from sims[0]'s options.
+ * Returns MCRT_ELIMIT (with valid results) if any packet hit its event cap. */
+int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_lambda, uint64_t seed,
+                        mcrt_result *const *results);
+
+/* Launch tuning of a sim (overrides its options' queue parameters). */
+typedef struct {
+    int32_t chunk;        /* packets per work-queue grab */
+    int32_t waves_per_cu; /* persistent waves per compute unit */
+    int32_t threshold;    /* lanes that must finish a march before events run */
+    double kernel_ms;     /* trial time of this setting (output of the tuner) */
+    int32_t from_cache;   /* 1 if the tuner found the setting in its cache */
+} mcrt_tuning;
+
+int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
+
+/* Autotuner: coordinate search over chunk {32..512}, threshold {8..48} and
+ * waves per CU {8, 12, 16} with short trial runs of trial_packets[i] packets
+ * per wavelength of each sim (one sim: the single-model kernel; several: the
+ * batched kernel), keeping the fastest.  With cache_path (may be NULL) the
+ * result is stored under a key describing the problem class (grid type,
+ * precision, model count, cells, wavelengths, instruments) and reused on the
+ * next call without trials.  The tuning is applied to every sim and returned
+ * in *best.  Results do not depend on the tuning beyond the order of atomic
+ * additions. */
+int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packets, uint64_t seed,
+                  const char *cache_path, mcrt_tuning *best);
+
 /* Absorbed luminosity table, out[i * n_lambda + j] for cell i and
  * wavelength j (Section 5.2, ParallelTable element (i, j)); count >=
  * n_cells * n_lambda. */

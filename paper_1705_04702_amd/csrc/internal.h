@@ -46,3 +46,33 @@ template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);
 
 } // namespace mcrt
+
+namespace mcrt {
+
+// One model of a batched launch: its scene view (pointers to global optics and
+// instrument arrays), its packet range and its own tally accumulators.
+template <typename Real, typename ImgT> struct ModelDesc {
+    View<Real, ImgT, 0> view;
+    const Optics<Real> *optics;
+    const InsDesc<Real> *ins;
+    uint64_t count;       // packets per wavelength in this launch
+    uint64_t first_id;
+    uint64_t total;       // count * n_lambda
+    uint64_t chunk0;      // index of the model's first chunk in the batch queue
+    double *energy;       // [4]
+    unsigned long long *stats; // [kNumStats]
+};
+
+template <typename Real, typename ImgT> struct BatchArgs {
+    const ModelDesc<Real, ImgT> *models;
+    int n_models;
+    uint64_t total_chunks;
+    uint32_t chunk;
+    int threshold;
+    unsigned long long *counter;
+};
+
+hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream);
+hipError_t launch_batch_f64(const BatchArgs<double, double> &a, int grid, hipStream_t stream);
+
+} // namespace mcrt

@@ -64,6 +64,7 @@ typedef struct {
     double tau_peel_max;
     int32_t precision;        // 0 FP32, 1 FP64
     int32_t top_level;        // -1 default
+    uint32_t model;           // fourth word of the Philox counter
 } ls_scene;
 
 typedef struct {
@@ -148,7 +149,7 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     v.octree_guard = 16 * 3 * (1 << depth) + 64;
     v.key0 = (uint32_t)(seed & 0xffffffffu);
     v.key1 = (uint32_t)(seed >> 32);
-    v.model = 0;
+    v.model = s->model;
 
     HostSink sink;
     Tally ty{};

@@ -8,7 +8,9 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -655,6 +657,257 @@ int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint6
     }
     if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res);
     return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res);
+}
+
+template <typename Real, typename ImgT>
+static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uint64_t seed, mcrt_result *const *res)
+{
+    mcrt_sim *s0 = sims[0];
+    hipStream_t st = s0->ctx->stream;
+    const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? s0->opt.chunk : 256);
+    std::vector<ModelDesc<Real, ImgT>> md((size_t)n);
+    uint64_t chunk0 = 0;
+    for (int i = 0; i < n; ++i) {
+        mcrt_sim *s = sims[i];
+        const mcrt_medium *m = s->medium;
+        const mcrt_grid *g = m->grid;
+        std::vector<Optics<Real>> optics((size_t)m->n_lambda);
+        for (int l = 0; l < m->n_lambda; ++l)
+            optics[l] = Optics<Real>{(Real)m->kappa[l], (Real)m->albedo[l], (Real)m->g[l],
+                                     (Real)(s->source->L[l] / (double)npl[i])};
+        HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
+        ModelDesc<Real, ImgT> &d = md[(size_t)i];
+        d = ModelDesc<Real, ImgT>{};
+        View<Real, ImgT, kCartesian> &v = d.view;
+        for (int c = 0; c < 3; ++c) {
+            v.bs[c] = s->bs[c];
+            v.nb[c] = s->nb[c];
+            v.n[c] = g->n[c];
+            v.lo[c] = (Real)g->box[c];
+            v.hi[c] = (Real)g->box[3 + c];
+            v.cs[c] = (Real)((g->box[3 + c] - g->box[c]) / (double)g->n[c]);
+            v.src_pos[c] = (Real)s->source->pos[c];
+        }
+        v.density = s->d_density;
+        v.n_cells = g->n_cells;
+        v.n_store = s->n_store;
+        v.n_lambda = m->n_lambda;
+        v.src_type = s->source->type;
+        v.hR = (Real)s->source->hR;
+        v.zs = (Real)s->source->zs;
+        v.n_ins = s->n_ins;
+        v.table = res[i]->d_table;
+        v.images = (ImgT *)res[i]->d_images;
+        v.w_min = (Real)s->opt.w_min;
+        v.event_cap = s->opt.event_cap;
+        v.tau_peel_max = (Real)s->opt.tau_peel_max;
+        v.octree_guard = 64;
+        v.key0 = (uint32_t)(seed & 0xffffffffu);
+        v.key1 = (uint32_t)(seed >> 32);
+        v.model = (uint32_t)i;
+        d.optics = (const Optics<Real> *)s->d_optics;
+        d.ins = (const InsDesc<Real> *)s->d_ins;
+        d.count = npl[i];
+        d.first_id = 0;
+        d.total = npl[i] * (uint64_t)m->n_lambda;
+        d.chunk0 = chunk0;
+        d.energy = res[i]->d_energy;
+        d.stats = res[i]->d_stats;
+        chunk0 += (d.total + chunk - 1) / chunk;
+    }
+    void *dmd = nullptr;
+    int rc = dev_alloc(&dmd, md.size() * sizeof(ModelDesc<Real, ImgT>));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(dmd, md.data(), md.size() * sizeof(ModelDesc<Real, ImgT>), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill_zero(res[0]->d_counter, sizeof(unsigned long long), st));
+    BatchArgs<Real, ImgT> a{};
+    a.models = (const ModelDesc<Real, ImgT> *)dmd;
+    a.n_models = n;
+    a.total_chunks = chunk0;
+    a.chunk = chunk;
+    a.threshold = s0->opt.threshold > 0 ? s0->opt.threshold : 16;
+    a.counter = res[0]->d_counter;
+    int wpc = s0->opt.waves_per_cu > 0 ? s0->opt.waves_per_cu : 16;
+    uint64_t waves = (uint64_t)s0->ctx->n_cu * (uint64_t)wpc;
+    if (waves > chunk0) waves = chunk0;
+    int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
+    if (grid < 1) grid = 1;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    hipError_t le;
+    if constexpr (sizeof(Real) == 4) le = launch_batch_f32(a, grid, st);
+    else le = launch_batch_f64(a, grid, st);
+    HIP_TRY(le);
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free(dmd);
+    bool capped = false;
+    for (int i = 0; i < n; ++i) {
+        res[i]->kernel_ms = ms;
+        unsigned long long stt[kNumStats];
+        HIP_TRY(hipMemcpy(stt, res[i]->d_stats, sizeof(stt), hipMemcpyDeviceToHost));
+        if (stt[7] > 0) capped = true;
+    }
+    if (capped) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
+    return MCRT_OK;
+}
+
+int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_lambda, uint64_t seed,
+                        mcrt_result *const *results)
+{
+    if (!sims || !n_per_lambda || !results || n <= 0) return fail(MCRT_EINVAL, "batch_run_into: NULL argument or n <= 0");
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i] || !results[i] || results[i]->sim != sims[i])
+            return fail(MCRT_EINVAL, "batch_run_into: result " + std::to_string(i) + " does not belong to its sim");
+        if (sims[i]->ctx != sims[0]->ctx || sims[i]->opt.precision != sims[0]->opt.precision)
+            return fail(MCRT_EINVAL, "batch_run_into: sims must share context and precision");
+        if (sims[i]->medium->grid->type != kCartesian)
+            return fail(MCRT_EINVAL, "batch_run_into: batched runs take Cartesian grids");
+        if (n_per_lambda[i] == 0 || n_per_lambda[i] > (uint64_t(1) << 32))
+            return fail(MCRT_EINVAL, "batch_run_into: n_per_lambda must be in 1 .. 2^32");
+    }
+    std::vector<std::unique_ptr<BusyGuard>> guards;
+    for (int i = 0; i < n; ++i) {
+        guards.emplace_back(new BusyGuard(sims[i]->busy));
+        if (!guards.back()->owned) return fail(MCRT_EBUSY, "batch_run_into: a simulation is already running (or listed twice)");
+    }
+    HIP_TRY(hipSetDevice(sims[0]->ctx->device));
+    if (sims[0]->opt.precision == MCRT_FP32) return batch_impl<float, float>(sims, n, n_per_lambda, seed, results);
+    return batch_impl<double, double>(sims, n, n_per_lambda, seed, results);
+}
+
+int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t)
+{
+    if (!sim || !t) return fail(MCRT_EINVAL, "sim_set_tuning: NULL argument");
+    if (t->chunk <= 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64)
+        return fail(MCRT_EINVAL, "sim_set_tuning: values out of range");
+    sim->opt.chunk = t->chunk;
+    sim->opt.waves_per_cu = t->waves_per_cu;
+    sim->opt.threshold = t->threshold;
+    return MCRT_OK;
+}
+
+static std::string tune_key(mcrt_sim *const *sims, int32_t n)
+{
+    int64_t cells = 0;
+    int nl = 0, nins = 0;
+    for (int i = 0; i < n; ++i) {
+        cells += sims[i]->medium->grid->n_cells;
+        nl = std::max(nl, sims[i]->medium->n_lambda);
+        nins = std::max(nins, sims[i]->n_ins);
+    }
+    int lc = 0;
+    while ((int64_t(1) << lc) < cells) lc++;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "grid=%s prec=%s models=%d cells=2^%d lambda=%d ins=%d",
+                  sims[0]->medium->grid->type == kOctree ? "octree" : "cartesian",
+                  sims[0]->opt.precision == MCRT_FP32 ? "fp32" : "fp64", n, lc, nl, nins);
+    return buf;
+}
+
+int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packets, uint64_t seed,
+                  const char *cache_path, mcrt_tuning *best)
+{
+    if (!sims || n <= 0 || !trial_packets || !best) return fail(MCRT_EINVAL, "autotune: NULL argument or n <= 0");
+    const std::string key = tune_key(sims, n);
+    if (cache_path) {
+        std::FILE *f = std::fopen(cache_path, "r");
+        if (f) {
+            char line[512];
+            while (std::fgets(line, sizeof(line), f)) {
+                char *bar = std::strchr(line, '|');
+                if (!bar) continue;
+                *bar = 0;
+                mcrt_tuning t{};
+                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf", &t.chunk, &t.waves_per_cu, &t.threshold,
+                                               &t.kernel_ms) == 4) {
+                    std::fclose(f);
+                    t.from_cache = 1;
+                    for (int i = 0; i < n; ++i) {
+                        int rc = mcrt_sim_set_tuning(sims[i], &t);
+                        if (rc) return rc;
+                    }
+                    *best = t;
+                    return MCRT_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    std::vector<mcrt_result *> res((size_t)n, nullptr);
+    auto cleanup = [&]() {
+        for (auto *r : res) mcrt_result_destroy(r);
+    };
+    for (int i = 0; i < n; ++i) {
+        int rc = mcrt_result_create(sims[i], &res[(size_t)i]);
+        if (rc) {
+            cleanup();
+            return rc;
+        }
+    }
+    auto trial = [&](const mcrt_tuning &t, double &ms) -> int {
+        for (int i = 0; i < n; ++i) {
+            int rc = mcrt_sim_set_tuning(sims[i], &t);
+            if (rc) return rc;
+        }
+        int rc;
+        if (n == 1) rc = mcrt_run_into(sims[0], trial_packets[0], 0, trial_packets[0], seed, res[0]);
+        else rc = mcrt_batch_run_into(sims, n, trial_packets, seed, res.data());
+        if (rc != MCRT_OK && rc != MCRT_ELIMIT) return rc;
+        ms = res[0]->kernel_ms;
+        return MCRT_OK;
+    };
+    mcrt_tuning cur{256, 16, 16, 0.0, 0};
+    double ms = 0.0;
+    int rc = trial(cur, ms); // warm-up
+    if (!rc) rc = trial(cur, ms);
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    cur.kernel_ms = ms;
+    const int chunks[] = {32, 64, 128, 256, 512};
+    const int thresholds[] = {8, 16, 32, 48};
+    const int waves[] = {8, 12, 16};
+    for (int pass = 0; pass < 3 && !rc; ++pass) {
+        const int *vals = pass == 0 ? chunks : pass == 1 ? thresholds : waves;
+        int nv = pass == 0 ? 5 : pass == 1 ? 4 : 3;
+        for (int k = 0; k < nv; ++k) {
+            mcrt_tuning t = cur;
+            if (pass == 0) t.chunk = vals[k];
+            else if (pass == 1) t.threshold = vals[k];
+            else t.waves_per_cu = vals[k];
+            if (t.chunk == cur.chunk && t.threshold == cur.threshold && t.waves_per_cu == cur.waves_per_cu) continue;
+            rc = trial(t, ms);
+            if (rc) break;
+            if (ms < cur.kernel_ms) {
+                cur = t;
+                cur.kernel_ms = ms;
+            }
+        }
+    }
+    cleanup();
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = mcrt_sim_set_tuning(sims[i], &cur);
+        if (rc) return rc;
+    }
+    cur.from_cache = 0;
+    *best = cur;
+    if (cache_path) {
+        std::FILE *f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%s|%d %d %d %.6f\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold, cur.kernel_ms);
+            std::fclose(f);
+        }
+    }
+    return MCRT_OK;
 }
 
 int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,

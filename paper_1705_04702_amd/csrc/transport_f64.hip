@@ -12,4 +12,8 @@ hipError_t launch_transport_f64o(const TransportArgs<double, double, 1> &a, int 
 {
     return launch_transport_impl<double, double, 1>(a, grid, stream);
 }
+hipError_t launch_batch_f64(const BatchArgs<double, double> &a, int grid, hipStream_t stream)
+{
+    return launch_batch_impl<double, double>(a, grid, stream);
+}
 } // namespace mcrt

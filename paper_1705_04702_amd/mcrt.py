@@ -31,6 +31,7 @@ EXPORTS = [
     "mcrt_result_zero", "mcrt_run_into", "mcrt_run", "mcrt_run_range", "mcrt_result_absorption",
     "mcrt_result_image", "mcrt_result_energy", "mcrt_result_stats", "mcrt_result_destroy",
     "mcrt_sim_info", "mcrt_last_error", "mcrt_microbench", "mcrt_microbench_error",
+    "mcrt_batch_run_into", "mcrt_sim_set_tuning", "mcrt_autotune",
 ]
 
 
@@ -56,6 +57,11 @@ class Options(ctypes.Structure):
 
 STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
                "peel_dropped", "capped", "guard"]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -116,6 +122,11 @@ def lib():
         "mcrt_microbench": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.POINTER(ctypes.c_double)]),
         "mcrt_microbench_error": (ctypes.c_char_p, []),
+        "mcrt_batch_run_into": (ctypes.c_int, [PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
+                                               ctypes.c_uint64, PP]),
+        "mcrt_sim_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "mcrt_autotune": (ctypes.c_int, [PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
+                                         ctypes.c_char_p, ctypes.POINTER(Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -297,6 +308,10 @@ class Sim:
         self.image_shapes = [(self.n_lambda, ins.npix[1], ins.npix[0]) for ins in scene.instruments]
         self.precision = precision
 
+    def set_tuning(self, chunk: int, waves_per_cu: int, threshold: int):
+        t = Tuning(chunk, waves_per_cu, threshold, 0.0, 0)
+        _check(lib().mcrt_sim_set_tuning(self.h, ctypes.byref(t)))
+
     def new_result(self) -> Result:
         r = ctypes.c_void_p()
         _check(lib().mcrt_result_create(self.h, ctypes.byref(r)))
@@ -335,6 +350,31 @@ class Sim:
             if h:
                 fn(h)
                 setattr(self, name, None)
+
+
+def _handles(objs):
+    return (ctypes.c_void_p * len(objs))(*[o.h.value if isinstance(o.h, ctypes.c_void_p) else o.h
+                                           for o in objs])
+
+
+def batch_run_into(sims: Sequence["Sim"], results: Sequence[Result], n_per_lambda: Sequence[int],
+                   seed: int = 0) -> int:
+    """One persistent launch over many sims (model index = position)."""
+    n = len(sims)
+    npl = (ctypes.c_uint64 * n)(*[int(x) for x in n_per_lambda])
+    return _check(lib().mcrt_batch_run_into(_handles(sims), n, npl, int(seed), _handles(results)),
+                  allow=(ELIMIT,))
+
+
+def autotune(sims: Sequence["Sim"], trial_packets: Sequence[int], seed: int = 0,
+             cache_path: Optional[str] = None) -> dict:
+    n = len(sims)
+    tp = (ctypes.c_uint64 * n)(*[int(x) for x in trial_packets])
+    t = Tuning()
+    _check(lib().mcrt_autotune(_handles(sims), n, tp, int(seed),
+                               cache_path.encode() if cache_path else None, ctypes.byref(t)))
+    return {"chunk": t.chunk, "waves_per_cu": t.waves_per_cu, "threshold": t.threshold,
+            "kernel_ms": t.kernel_ms, "from_cache": bool(t.from_cache)}
 
 
 def run_scene(scene, n_per_lambda: int, seed: int = 0, precision: int = FP32, first_id: int = 0,

@@ -23,7 +23,7 @@ class _Scene(ctypes.Structure):
         ("n_ins", ctypes.c_int32), ("ins_geom", ctypes.POINTER(ctypes.c_double)),
         ("ins_npix", ctypes.POINTER(ctypes.c_int32)), ("w_min", ctypes.c_double),
         ("event_cap", ctypes.c_int64), ("tau_peel_max", ctypes.c_double),
-        ("precision", ctypes.c_int32), ("top_level", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("top_level", ctypes.c_int32), ("model", ctypes.c_uint32),
     ]
 
 
@@ -51,7 +51,7 @@ def lib():
     return _lib
 
 
-def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level=-1):
+def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level=-1, model=0):
     if count is None:
         count = n_per_lambda - first_id
     keep = []
@@ -91,6 +91,7 @@ def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level
     s.w_min, s.event_cap, s.tau_peel_max = sc.w_min, sc.event_cap, sc.tau_peel_max
     s.precision = precision
     s.top_level = top_level
+    s.model = model
     nl = s.n_lambda
     table = np.zeros(s.n_cells * nl)
     shapes = [(nl, i.npix[1], i.npix[0]) for i in sc.instruments]

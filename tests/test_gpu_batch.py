@@ -1,0 +1,134 @@
+"""GPU parity of the batched launch (many uneven models in one persistent
+launch) and of the autotuner, through the C-ABI.
+
+Model i of a batch draws its packets' random numbers with counter word 3 =
+i, so each model must match the oracle run with model = i: FP64 validation
+to 1e-9 per cell and pixel, FP32 within the Monte Carlo noise.  Results may
+not depend on the queue tuning beyond the order of atomic additions.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04702_amd import mcrt, scenes
+
+from test_gpu_parity import assert_fp64_parity, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = mcrt.Context(0)
+    yield c
+    c.close()
+
+
+def batch_models(n, packet_div=20000, npix=24, extra=True):
+    rows = scenes.batch_table(n, seed=4)
+    models = [scenes.batch_model(r, npix=npix) for r in rows]
+    packets = [max(1, r["packets"] // packet_div) for r in rows]
+    if extra:
+        # uneven extras: a multi-wavelength model and a one-packet model
+        models.append(scenes.disk((16, 16, 8), 3, npix))
+        packets.append(97)
+        models.append(scenes.sphere(n=8, npix=npix))
+        packets.append(1)
+    return models, packets
+
+
+def run_batch(ctx, models, packets, precision, seed=0, **tune):
+    sims = [mcrt.Sim(ctx, sc, precision, **tune) for sc in models]
+    res = [s.new_result() for s in sims]
+    say(f"batch of {len(sims)} models, packets {packets}, prec {precision}, {tune}")
+    rc = mcrt.batch_run_into(sims, res, packets, seed)
+    out = [{"table": r.table(), "images": r.images(), "energy": r.energy(), "stats": r.stats()} for r in res]
+    for s in sims:
+        s.close()
+    return rc, out
+
+
+def test_batch_fp64_parity(ctx):
+    models, packets = batch_models(10)
+    rc, out = run_batch(ctx, models, packets, mcrt.FP64_VALIDATE, seed=6, chunk=64)
+    assert rc == mcrt.OK
+    for i, (sc, n, g) in enumerate(zip(models, packets, out)):
+        o = oracle.run(sc, n, seed=6, model=i)
+        assert_fp64_parity(g, o)
+
+
+@pytest.mark.parametrize("tune", [dict(chunk=16, threshold=4, waves_per_cu=4),
+                                  dict(chunk=512, threshold=48, waves_per_cu=16)])
+def test_batch_tuning_invariance(ctx, tune):
+    models, packets = batch_models(6, packet_div=5000)
+    _, ref = run_batch(ctx, models, packets, mcrt.FP64_VALIDATE, seed=1, chunk=128)
+    _, got = run_batch(ctx, models, packets, mcrt.FP64_VALIDATE, seed=1, **tune)
+    for a, b in zip(got, ref):
+        np.testing.assert_allclose(a["table"], b["table"], rtol=1e-12, atol=0)
+        for x, y in zip(a["images"], b["images"]):
+            np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(a["energy"], b["energy"], rtol=1e-12)
+
+
+def test_batch_fp32_energy_and_totals(ctx):
+    models, packets = batch_models(8, packet_div=2000, extra=False)
+    rc, out = run_batch(ctx, models, packets, mcrt.FP32, seed=2)
+    assert rc == mcrt.OK
+    for i, (sc, n, g) in enumerate(zip(models, packets, out)):
+        e = g["energy"]
+        assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+        o = oracle.run(sc, n, seed=2, model=i, moments=True)
+        T = o["table"]
+        sig = np.sqrt(max((o["table_m2"] - T * T / n).sum(), 0.0))
+        assert abs(e[1] - o["energy"][1]) <= 1e-5 * o["energy"][1] + 4 * sig
+        assert g["stats"]["packets"] == n
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    models, packets = batch_models(6, packet_div=2000, extra=False)
+    sims = [mcrt.Sim(ctx, sc, mcrt.FP32) for sc in models]
+    cache = str(tmp_path / "tune.txt")
+    try:
+        t1 = mcrt.autotune(sims, [max(1, p // 4) for p in packets], seed=3, cache_path=cache)
+        say(f"autotune: {t1}")
+        assert not t1["from_cache"]
+        assert t1["chunk"] in (32, 64, 128, 256, 512) and t1["threshold"] in (8, 16, 32, 48)
+        assert t1["waves_per_cu"] in (8, 12, 16) and t1["kernel_ms"] > 0
+        t2 = mcrt.autotune(sims, [1] * len(sims), seed=3, cache_path=cache)
+        assert t2["from_cache"] and (t2["chunk"], t2["threshold"], t2["waves_per_cu"]) == \
+            (t1["chunk"], t1["threshold"], t1["waves_per_cu"])
+        assert open(cache).read().count("|") == 1
+        # single-model tuning uses the single-model kernel
+        t3 = mcrt.autotune(sims[:1], [max(1, packets[0] // 4)], seed=3)
+        assert t3["chunk"] > 0
+    finally:
+        for s in sims:
+            s.close()
+
+
+def test_batch_errors(ctx):
+    a = mcrt.Sim(ctx, scenes.sphere(n=8), mcrt.FP32)
+    b = mcrt.Sim(ctx, scenes.sphere(n=8), mcrt.FP64_VALIDATE)
+    t = mcrt.Sim(ctx, scenes.torus(4, 3, 1, 8, n_clumps=5), mcrt.FP32)
+    try:
+        ra, rb, rt = a.new_result(), b.new_result(), t.new_result()
+        with pytest.raises(mcrt.MCRTError) as ei:  # mixed precision
+            mcrt.batch_run_into([a, b], [ra, rb], [10, 10])
+        assert ei.value.code == mcrt.EINVAL
+        with pytest.raises(mcrt.MCRTError) as ei:  # octree model
+            mcrt.batch_run_into([a, t], [ra, rt], [10, 10])
+        assert ei.value.code == mcrt.EINVAL
+        with pytest.raises(mcrt.MCRTError) as ei:  # result of another sim
+            mcrt.batch_run_into([a], [rb], [10])
+        assert ei.value.code == mcrt.EINVAL
+        with pytest.raises(mcrt.MCRTError) as ei:  # the same sim twice
+            mcrt.batch_run_into([a, a], [ra, ra], [10, 10])
+        assert ei.value.code == mcrt.EBUSY
+    finally:
+        for s in (a, b, t):
+            s.close()

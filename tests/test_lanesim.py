@@ -72,3 +72,15 @@ def test_lane_logic_fp32_statistical():
     bad = np.abs(l["table"][sel, 0] - T[sel]) > 3 * np.sqrt(var[sel])
     assert bad.mean() <= 0.005
     assert abs(l["energy"][1] - o["energy"][1]) / o["energy"][1] < 1e-3
+
+
+def test_model_index_enters_the_streams():
+    """The batch position is the fourth Philox counter word: the lane code
+    with model = b reproduces the oracle run with model = b, and differs from
+    model 0."""
+    sc = scenes.batch_model(scenes.batch_table(3, seed=4)[2])
+    o = oracle.run(sc, 300, seed=3, model=2)
+    l = lanesim.run(sc, 300, seed=3, precision=1, model=2)
+    np.testing.assert_array_equal(l["table"], o["table"])
+    o0 = oracle.run(sc, 300, seed=3, model=0)
+    assert not np.array_equal(o0["table"], o["table"])

@@ -50,15 +50,73 @@ def algorithmic_bytes(st: dict) -> int:
             + B_PIXEL * st["peel_adds"])
 
 
+WORKLOADS = {
+    # name: (packets per wavelength of the whole job, description)
+    "disk": (10_000_000, "exponential-disk galaxy: 256^3 Cartesian grid, 64 wavelengths 0.1-1000 um, "
+                         "3 x 512^2 instruments (i = 0/60/90 deg), 1e7 packets per wavelength, "
+                         "FP32 transport, FP64 table totals"),
+    "sphere": (100_000, "uniform sphere tau=1, albedo 0.5, g=0.5: 32^3 grid, 1 wavelength, "
+                        "64^2 instrument at 100 radii, 1e5 packets"),
+    "torus": (3_125_000, "clumpy AGN torus: octree (~2.2e6 leaves, depth 9), 3% clumps of 0.4 pc, "
+                         "contrast 100, equatorial tau_V=50, anisotropic source, 32 wavelengths, "
+                         "1e8 packets, 1024^2 edge-on instrument"),
+}
+
+
 def make_scene(name: str):
     from paper_1705_04702_amd import scenes
     if name == "disk":
-        return scenes.disk(), ("exponential-disk galaxy: 256^3 Cartesian grid, 64 wavelengths "
-                               "0.1-1000 um, 3 x 512^2 instruments (i = 0/60/90 deg), "
-                               "1e7 packets per wavelength, FP32 transport, FP64 table totals")
+        return scenes.disk(), WORKLOADS[name][1]
     if name == "sphere":
-        return scenes.sphere(), "uniform sphere tau=1: 32^3 grid, 1 wavelength, 64^2 instrument"
+        return scenes.sphere(), WORKLOADS[name][1]
+    if name == "torus":
+        return scenes.torus(), WORKLOADS[name][1]
     raise SystemExit(f"unknown workload {name}")
+
+
+def bench_batch(args):
+    """256 uneven uniform-sphere / exponential-slab models (16^3 .. 128^3,
+    1e5 .. 1e7 packets each, 128^2 images) in one persistent launch per step."""
+    import torch
+    from paper_1705_04702_amd import mcrt, scenes
+    models = scenes.batch(256, seed=4)
+    ctx = mcrt.Context(0)
+    sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32) for m in models]
+    npl = [m.n_packets for m in models]
+    tuning = None
+    if args.autotune:
+        tuning = mcrt.autotune(sims, [max(1, n // 100) for n in npl], seed=0,
+                               cache_path=os.path.join(ROOT, "_build", "tune_cache.txt"))
+        print(f"[bench] autotune {tuning}", file=sys.stderr, flush=True)
+    res = [s.new_result() for s in sims]
+    for w in range(args.warmup):
+        mcrt.batch_run_into(sims, res, npl, seed=0)
+    for r in res:
+        r.zero()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for k in range(args.steps):
+        mcrt.batch_run_into(sims, res, npl, seed=0)
+        kms.append(res[0].stats()["kernel_ms"])
+        print(f"[bench] batch step {k}: kernel {kms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    packets = sum(npl) * args.steps
+    worst = max(abs(e[0] - e[1] - e[2] - e[3]) / e[0] for e in (r.energy() for r in res))
+    sts = [r.stats() for r in res]
+    deposits = sum(s["prop_cells"] for s in sts) / args.steps
+    out = {"metric": METRIC, "value": packets / T, "unit": "packets/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch of 256 uniform-sphere / exponential-slab models, grids 16^3-128^3 "
+                                  "log-uniform, tau 0.1-20, packets 1e5-1e7 each (total %d), 128^2 images, "
+                                  "one persistent launch" % sum(npl), "models": 256},
+           "kernel_ms_avg": sum(kms) / len(kms), "energy_balance_worst": worst,
+           "atomics_per_s": deposits / (sum(kms) / len(kms) / 1e3), "tuning": tuning}
+    for s in sims:
+        s.close()
+    print(json.dumps(out), flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -128,7 +186,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="disk")
-    ap.add_argument("--n-per-lambda", type=int, default=10_000_000)
+    ap.add_argument("--n-per-lambda", type=int, default=0, help="0 = the workload's own")
+    ap.add_argument("--autotune", action="store_true", help="tune the queue before timing")
     ap.add_argument("--step-packets", type=int, default=1_000_000,
                     help="packet ids per wavelength in one step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -163,14 +222,21 @@ def main():
     from paper_1705_04702_amd import mcrt
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     scene, workload = make_scene(args.workload)
-    N = args.n_per_lambda
+    N = args.n_per_lambda or WORKLOADS[args.workload][0]
     B = min(args.step_packets, N)
     ctx = mcrt.Context(0)
     brick = tuple(int(x) for x in args.brick.split(",")) if args.brick else None
     sim = mcrt.Sim(ctx, scene, mcrt.FP32, chunk=args.chunk or None,
                    waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None,
                    brick=brick)
+    if args.autotune:
+        t = mcrt.autotune([sim], [max(1, min(N, B) // 20)], seed=0,
+                          cache_path=os.path.join(ROOT, "_build", "tune_cache.txt"))
+        print(f"[bench] autotune {t}", file=sys.stderr, flush=True)
     res = sim.new_result()
     nl = scene.n_lambda
     print(f"[bench] workload={args.workload} n_lambda={nl} step={B} ids/lambda "

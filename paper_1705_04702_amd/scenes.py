@@ -235,7 +235,7 @@ def torus(max_depth: int = 9, torus_depth: int = 8, n_lambda: int = 32, npix: in
           seed: int = 3, clump_radius: float = 0.4, fill: float = 0.03,
           contrast: float = 100.0, tau_eq: float = 50.0, r_in: float = 0.5,
           r_out: float = 15.0, half_open_deg: float = 40.0, incl_deg: float = 90.0,
-          n_clumps: Optional[int] = None) -> Scene:
+          n_clumps: Optional[int] = None, min_depth: Optional[int] = None) -> Scene:
     """Clumpy two-phase wedge torus (pc units) on an octree over [-15, 15]^3.
 
     The medium is voxelised on the 2^max_depth lattice at voxel centres:
@@ -248,6 +248,8 @@ def torus(max_depth: int = 9, torus_depth: int = 8, n_lambda: int = 32, npix: in
     = tau_eq with rho_mean = rho_ic (1 + fill (contrast - 1)).
     """
     rng = np.random.default_rng(seed)
+    if min_depth is None:
+        min_depth = max_depth - 2
     half = r_out
     box = (-half, -half, -half, half, half, half)
     N = 1 << max_depth
@@ -304,7 +306,7 @@ def torus(max_depth: int = 9, torus_depth: int = 8, n_lambda: int = 32, npix: in
         mx = pmax[level][iz, iy, ix]
         mixed = mn != mx
         lim = np.where(mx == 2, max_depth, torus_depth)
-        return mixed & (level < lim)
+        return (mixed & (level < lim)) | ((mx >= 1) & (level < min_depth))
 
     first_child, (lv, lx, ly, lz), depth = octree_from_levels(refine, max_depth)
     dens = np.empty(lv.shape[0], dtype=np.float64)

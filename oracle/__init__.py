@@ -63,6 +63,12 @@ class _Scene(ctypes.Structure):
         ("w_min", ctypes.c_double),
         ("event_cap", ctypes.c_int64),
         ("tau_peel_max", ctypes.c_double),
+        ("mlp", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.c_double),
+        ("lambda_um", ctypes.POINTER(ctypes.c_double)),
+        ("r_out", ctypes.c_double),
+        ("lam_feature", ctypes.POINTER(ctypes.c_double)),
+        ("rho_mean", ctypes.c_double),
     ]
 
 
@@ -80,6 +86,9 @@ class _Out(ctypes.Structure):
         ("table_m2", ctypes.POINTER(ctypes.c_double)),
         ("image_m2", ctypes.POINTER(ctypes.c_double)),
         ("stats", _Stats),
+        ("hist", ctypes.POINTER(ctypes.c_double)),
+        ("hist_total", ctypes.POINTER(ctypes.c_double)),
+        ("hist_events", ctypes.c_int32),
     ]
 
 
@@ -106,6 +115,8 @@ def lib():
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
         L.or_march.restype = ctypes.c_int64
+        L.or_mlp_forward.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
+        L.or_mlp_forward.restype = None
         L.or_hg_phase.argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_hg_phase.restype = ctypes.c_double
         L.or_hg_sample.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -166,11 +177,13 @@ class _SceneHolder:
         s.w_min = float(sc.w_min)
         s.event_cap = int(sc.event_cap)
         s.tau_peel_max = float(sc.tau_peel_max)
+        self.lambdas = np.ascontiguousarray(sc.lambdas, dtype=np.float64)
+        s.lambda_um = _ptr(self.lambdas, ctypes.c_double)
         self.s = s
 
 
 def run(scene, n_per_lambda: int, seed: int = 0, first_id: int = 0, count=None,
-        model: int = 0, moments: bool = False):
+        model: int = 0, moments: bool = False, mlp=None, alpha: float = 0.2, histories: int = 0):
     """Runs packet ids [first_id, first_id + count) of every wavelength.
 
     Returns a dict with ``table`` [n_cells, n_lambda] (element (i, j) = cell i,
@@ -181,6 +194,11 @@ def run(scene, n_per_lambda: int, seed: int = 0, first_id: int = 0, count=None,
     if count is None:
         count = n_per_lambda - first_id
     h = _SceneHolder(scene)
+    if mlp is not None:
+        from oracle import learned
+        h.mlp = np.ascontiguousarray(learned.round_weights(np.asarray(mlp, dtype=np.float64)))
+        h.s.mlp = _ptr(h.mlp, ctypes.c_double)
+        h.s.alpha = float(alpha)
     nl = h.s.n_lambda
     table = np.zeros(h.s.n_cells * nl, dtype=np.float64)
     shapes = [(nl, i.npix[1], i.npix[0]) for i in scene.instruments]
@@ -196,6 +214,13 @@ def run(scene, n_per_lambda: int, seed: int = 0, first_id: int = 0, count=None,
         im2 = np.zeros_like(images)
         out.table_m2 = _ptr(tm2, ctypes.c_double)
         out.image_m2 = _ptr(im2, ctypes.c_double)
+    if histories:
+        npk = int(count) * nl
+        hist = np.zeros(npk * histories * 14)
+        htot = np.zeros(npk)
+        out.hist = _ptr(hist, ctypes.c_double)
+        out.hist_total = _ptr(htot, ctypes.c_double)
+        out.hist_events = int(histories)
     rc = lib().or_run(ctypes.byref(h.s), int(n_per_lambda), int(first_id), int(count),
                       int(seed), int(model), ctypes.byref(out))
     if rc != 0:
@@ -209,7 +234,19 @@ def run(scene, n_per_lambda: int, seed: int = 0, first_id: int = 0, count=None,
     if moments:
         res["table_m2"] = tm2.reshape(h.s.n_cells, nl)
         res["image_m2"] = _split(im2, shapes)
+    if histories:
+        res["hist"] = hist.reshape(-1, histories, 14)
+        res["hist_total"] = htot
     return res
+
+
+def mlp_forward(theta, f):
+    """The C oracle's network evaluation (bf16-rounded inputs/activations)."""
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    x = np.ascontiguousarray(f, dtype=np.float64)
+    o = np.zeros(40)
+    lib().or_mlp_forward(_ptr(t, ctypes.c_double), _ptr(x, ctypes.c_double), _ptr(o, ctypes.c_double))
+    return o
 
 
 def _split(flat, shapes):

@@ -593,6 +593,122 @@ void or_rotate(const double k[3], double mu, double phi, double out[3])
     out[2] = z / nrm;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Learned direction proposal: MLP 9 -> 64 -> 64 -> 40 (ReLU) giving an      */
+/* 8-lobe von Mises-Fisher mixture, mixed with the physical distribution.    */
+/* ------------------------------------------------------------------------ */
+
+static const double INV_LN10 = 0.43429448190325182765;
+
+/* nearest-even to float32, then nearest-even to bfloat16 */
+static double bf16_round(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, sizeof b);
+    uint32_t lsb = (b >> 16) & 1u;
+    b = ((b + 0x7FFFu + lsb) >> 16) << 16;
+    memcpy(&f, &b, sizeof f);
+    return (double)f;
+}
+
+/* z_j = sum_k x_k W[k][j] (k in order, from 0) + b_j */
+static void affine(const double *x, int nin, const double *W, const double *b, int nout, double *z)
+{
+    for (int j = 0; j < nout; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < nin; ++k) acc = acc + x[k] * W[k * nout + j];
+        z[j] = acc + b[j];
+    }
+}
+
+void or_mlp_forward(const double *theta, const double f[9], double out[40])
+{
+    const double *W1 = theta, *b1 = W1 + 9 * 64, *W2 = b1 + 64, *b2 = W2 + 64 * 64;
+    const double *W3 = b2 + 64, *b3 = W3 + 64 * 40;
+    double x[9], z[64], h1[64], h2[64];
+    for (int k = 0; k < 9; ++k) x[k] = bf16_round(f[k]);
+    affine(x, 9, W1, b1, 64, z);
+    for (int j = 0; j < 64; ++j) h1[j] = bf16_round(z[j] > 0.0 ? z[j] : 0.0);
+    affine(h1, 64, W2, b2, 64, z);
+    for (int j = 0; j < 64; ++j) h2[j] = bf16_round(z[j] > 0.0 ? z[j] : 0.0);
+    affine(h2, 64, W3, b3, 40, out);
+}
+
+typedef struct {
+    double pi[8], mu[8][3], kappa[8];
+} mixture;
+
+static void mixture_from(const double o[40], mixture *m)
+{
+    double mx = o[0];
+    for (int j = 1; j < 8; ++j)
+        if (o[j] > mx) mx = o[j];
+    double e[8], sum = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        e[j] = or_exp(o[j] - mx);
+        sum = sum + e[j];
+    }
+    for (int j = 0; j < 8; ++j) {
+        m->pi[j] = e[j] / sum;
+        double a = o[8 + 3 * j], b = o[9 + 3 * j], c = o[10 + 3 * j];
+        double nrm = sqrt(a * a + b * b + c * c);
+        if (nrm > 0.0) {
+            m->mu[j][0] = a / nrm;
+            m->mu[j][1] = b / nrm;
+            m->mu[j][2] = c / nrm;
+        } else {
+            m->mu[j][0] = 0.0;
+            m->mu[j][1] = 0.0;
+            m->mu[j][2] = 1.0;
+        }
+        double s = o[32 + j];
+        double sp = or_log1p(or_exp(-fabs(s))) + (s > 0.0 ? s : 0.0);
+        double k = sp + 1e-3;
+        if (k < 1e-3) k = 1e-3;
+        if (k > 1e3) k = 1e3;
+        m->kappa[j] = k;
+    }
+}
+
+/* density of the vMF part at direction kp */
+static double mixture_vmf_pdf(const mixture *m, const double kp[3])
+{
+    double q = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        double k = m->kappa[j];
+        double dot = m->mu[j][0] * kp[0] + m->mu[j][1] * kp[1] + m->mu[j][2] * kp[2];
+        double f = k / (2.0 * OR_PI * -or_expm1(-2.0 * k)) * or_exp(k * (dot - 1.0));
+        q = q + m->pi[j] * f;
+    }
+    return q;
+}
+
+/* With probability 1 - alpha (selector u3) a direction from the vMF part:
+ * lobe by the cumulative weights at (u3 - alpha)/(1 - alpha), cosine to its
+ * mean by the inverse CDF at u1, azimuth 2 pi u2.  Returns 1 if it sampled,
+ * 0 if the caller must draw from the physical distribution with (u1, u2). */
+static int mixture_sample(const mixture *m, double alpha, double u1, double u2, double u3, double kp[3])
+{
+    if (u3 < alpha) return 0;
+    double v = (u3 - alpha) / (1.0 - alpha), c = 0.0;
+    int j = 7;
+    for (int i = 0; i < 8; ++i) {
+        c = c + m->pi[i];
+        if (v < c) {
+            j = i;
+            break;
+        }
+    }
+    double k = m->kappa[j];
+    double w = 1.0 + or_log(u1 + (1.0 - u1) * or_exp(-2.0 * k)) / k;
+    if (w < -1.0) w = -1.0;
+    if (w > 1.0) w = 1.0;
+    or_rotate(m->mu[j], w, 2.0 * OR_PI * u2, kp);
+    return 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The packet life cycle.                                                    */
 /* ------------------------------------------------------------------------ */
@@ -641,6 +757,7 @@ typedef struct {
     moment_buf mt, mi;
     uint64_t seed;
     uint32_t model;
+    double flux;     /* image flux produced so far by the current packet */
 } runctx;
 
 /* Optical depth from r along k to the grid boundary. */
@@ -682,6 +799,7 @@ static int peel(runctx *c, int ell, const double r[3], double lum, double phase,
     double flux = lum * phase * or_exp(-tau) * in->inv4pid2;
     int64_t idx = in->offset + ((int64_t)ell * in->ny + (int64_t)py) * in->nx + (int64_t)px;
     c->out->images[idx] += flux;
+    c->flux += flux;
     moment_add(&c->mi, idx, flux);
     c->out->stats.peel_adds++;
     return 0;
@@ -693,7 +811,31 @@ static double source_phase(const or_scene *s, const double kobs[3])
     return 1.0;
 }
 
-static int one_packet(runctx *c, int ell, uint32_t id, double L0)
+/* Event features: position / r_out (3), incoming direction (3, zero at
+ * emission), wavelength feature, log10 of the cell density over the mean
+ * (0 at emission), event flag (0 emission, 1 scattering). */
+static void event_features(const or_scene *s, int ell, const double r[3], const double *kin, double rho,
+                           double f[9])
+{
+    for (int a = 0; a < 3; ++a) f[a] = r[a] / s->r_out;
+    for (int a = 0; a < 3; ++a) f[3 + a] = kin ? kin[a] : 0.0;
+    f[6] = s->lam_feature[ell];
+    f[7] = kin ? or_log(rho / s->rho_mean) * INV_LN10 : 0.0;
+    f[8] = kin ? 1.0 : 0.0;
+}
+
+static void record_event(runctx *c, int64_t slot, int64_t e, const double f[9], const double kp[3], double L)
+{
+    or_out *o = c->out;
+    if (!o->hist || e >= o->hist_events) return;
+    double *h = o->hist + (slot * o->hist_events + e) * 14;
+    for (int i = 0; i < 9; ++i) h[i] = f[i];
+    for (int i = 0; i < 3; ++i) h[9 + i] = kp[i];
+    h[12] = L;
+    h[13] = c->flux;
+}
+
+static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
 {
     const or_scene *s = c->s;
     or_out *o = c->out;
@@ -715,20 +857,7 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
         r[1] = s->src_pos[1];
         r[2] = s->src_pos[2];
     }
-    double mu;
-    if (s->source_type == OR_SRC_POINT_ANISO) {
-        double u5 = U(5);
-        mu = u5 < 0.5 ? sqrt(2.0 * u5) : -sqrt(2.0 * u5 - 1.0);
-    } else {
-        mu = 2.0 * U(5) - 1.0;
-    }
-    double phi = 2.0 * OR_PI * U(6);
-    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double sphi, cphi;
-    or_sincos(phi, &sphi, &cphi);
-    k[0] = st * cphi;
-    k[1] = st * sphi;
-    k[2] = mu;
+    c->flux = 0.0;
     o->energy[0] += L0;
     o->stats.packets++;
     /* emission peel-off */
@@ -736,7 +865,46 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
         int rc = peel(c, ell, r, L0, source_phase(s, c->ins[j].kobs), kappa, j);
         if (rc) return rc;
     }
+    /* emission direction: the source's angular distribution, or the learned
+     * proposal (point sources) with weight p_phys / q */
+    const int learned = s->mlp != NULL;
     double L = L0;
+    int use_phys = 1;
+    mixture mx;
+    if (learned && s->source_type != OR_SRC_EXPDISK) {
+        double f[9], out[40];
+        event_features(s, ell, r, NULL, 0.0, f);
+        or_mlp_forward(s->mlp, f, out);
+        mixture_from(out, &mx);
+        use_phys = !mixture_sample(&mx, s->alpha, U(5), U(6), U(7), k);
+    }
+    if (use_phys) {
+        double mu;
+        if (s->source_type == OR_SRC_POINT_ANISO) {
+            double u5 = U(5);
+            mu = u5 < 0.5 ? sqrt(2.0 * u5) : -sqrt(2.0 * u5 - 1.0);
+        } else {
+            mu = 2.0 * U(5) - 1.0;
+        }
+        double phi = 2.0 * OR_PI * U(6);
+        double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double sphi, cphi;
+        or_sincos(phi, &sphi, &cphi);
+        k[0] = st * cphi;
+        k[1] = st * sphi;
+        k[2] = mu;
+    }
+    if (learned && s->source_type != OR_SRC_EXPDISK) {
+        double S = s->source_type == OR_SRC_POINT_ANISO ? 2.0 * fabs(k[2]) : 1.0;
+        double pphys = S / (4.0 * OR_PI);
+        double q = s->alpha * pphys + (1.0 - s->alpha) * mixture_vmf_pdf(&mx, k);
+        L = L0 * (pphys / q);
+    }
+    if (!learned) {
+        double f[9];
+        event_features(s, ell, r, NULL, 0.0, f);
+        record_event(c, slot, 0, f, k, L0);
+    }
     int64_t e = 1;
     for (;;) {
         /* propagation to the boundary with continuous absorption */
@@ -798,8 +966,10 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
             taustar_prev = taulast_prev;
             start_star = start_last;
         }
+        double rho_star;
         {
             int64_t m = c->sl.cell[nstar];
+            rho_star = (double)s->density[m];
             double ds = c->sl.tend[nstar] - start_star;
             double inside = (tau_int - taustar_prev) / (kappa * (double)s->density[m]);
             if (inside < 0.0) inside = 0.0;
@@ -817,15 +987,34 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
             rc = peel(c, ell, r, Ls, or_hg_phase(g, cosang), kappa, j);
             if (rc) return rc;
         }
-        /* new direction */
-        double mus = or_hg_sample(g, U(8 * e + 1));
-        double phis = 2.0 * OR_PI * U(8 * e + 2);
-        double kn[3];
-        or_rotate(k, mus, phis, kn);
+        /* new direction: Henyey-Greenstein about k, or the learned proposal
+         * with weight p_phys / q */
+        double kn[3], f[9];
+        event_features(s, ell, r, k, rho_star, f);
+        int phys = 1;
+        if (learned) {
+            double out[40];
+            or_mlp_forward(s->mlp, f, out);
+            mixture_from(out, &mx);
+            phys = !mixture_sample(&mx, s->alpha, U(8 * e + 1), U(8 * e + 2), U(8 * e + 3), kn);
+        }
+        if (phys) {
+            double mus = or_hg_sample(g, U(8 * e + 1));
+            double phis = 2.0 * OR_PI * U(8 * e + 2);
+            or_rotate(k, mus, phis, kn);
+        }
+        if (learned) {
+            double cosang = k[0] * kn[0] + k[1] * kn[1] + k[2] * kn[2];
+            double pphys = or_hg_phase(g, cosang) / (4.0 * OR_PI);
+            double q = s->alpha * pphys + (1.0 - s->alpha) * mixture_vmf_pdf(&mx, kn);
+            L = Ls * (pphys / q);
+        } else {
+            L = Ls;
+            record_event(c, slot, e, f, kn, Ls);
+        }
         k[0] = kn[0];
         k[1] = kn[1];
         k[2] = kn[2];
-        L = Ls;
         e = e + 1;
         if (e > s->event_cap) {
             o->energy[3] += L;
@@ -834,6 +1023,7 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0)
         }
     }
 #undef U
+    if (c->out->hist_total) c->out->hist_total[slot] = c->flux;
     moment_flush(&c->mt);
     moment_flush(&c->mi);
     return 0;
@@ -866,10 +1056,35 @@ static void instruments_init(const or_scene *s, instr *ins)
     }
 }
 
-int or_run(const or_scene *s, uint64_t n_per_lambda, uint64_t first_id,
+/* Feature constants of the learned proposal, from the scene. */
+static void feature_constants(or_scene *s, double *lam_feature)
+{
+    double side = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (s->box[3 + a] - s->box[a] > side) side = s->box[3 + a] - s->box[a];
+    s->r_out = 0.5 * side;
+    double sum = 0.0;
+    for (int64_t m = 0; m < s->n_cells; ++m) sum = sum + (double)s->density[m];
+    s->rho_mean = sum / (double)s->n_cells;
+    double lmin = s->lambda_um[0], lmax = s->lambda_um[0];
+    for (int l = 1; l < s->n_lambda; ++l) {
+        if (s->lambda_um[l] < lmin) lmin = s->lambda_um[l];
+        if (s->lambda_um[l] > lmax) lmax = s->lambda_um[l];
+    }
+    for (int l = 0; l < s->n_lambda; ++l)
+        lam_feature[l] = lmax > lmin ? (log(s->lambda_um[l]) - log(lmin)) / (log(lmax) - log(lmin)) : 0.0;
+    s->lam_feature = lam_feature;
+}
+
+int or_run(const or_scene *s_in, uint64_t n_per_lambda, uint64_t first_id,
            uint64_t count, uint64_t seed, uint32_t model, or_out *out)
 {
-    if (!s || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
+    if (!s_in || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
+    if (s_in->mlp && !s_in->lambda_um) return -1;
+    or_scene scene = *s_in;
+    or_scene *s = &scene;
+    double *lam_feature = (double *)calloc((size_t)(s->n_lambda > 0 ? s->n_lambda : 1), sizeof(double));
+    if (s->lambda_um && s->n_lambda > 0) feature_constants(s, lam_feature);
     if (first_id + count > 0xffffffffull + 1ull) return -1;
     if (s->n_lambda <= 0 || s->n_cells <= 0 || s->n_ins < 0) return -1;
     runctx c;
@@ -901,7 +1116,7 @@ int or_run(const or_scene *s, uint64_t n_per_lambda, uint64_t first_id,
     for (int ell = 0; ell < s->n_lambda && rc == 0; ++ell) {
         double L0 = s->lum[ell] / (double)n_per_lambda;
         for (uint64_t i = first_id; i < first_id + count; ++i) {
-            rc = one_packet(&c, ell, (uint32_t)i, L0);
+            rc = one_packet(&c, ell, (uint32_t)i, L0, (int64_t)ell * (int64_t)count + (int64_t)(i - first_id));
             if (rc) break;
         }
     }
@@ -910,6 +1125,7 @@ int or_run(const or_scene *s, uint64_t n_per_lambda, uint64_t first_id,
     free(c.mi.acc);
     free(c.mi.touched);
     free(c.ins);
+    free(lam_feature);
     seg_free(&c.sl);
     geom_free(&c.g);
     return rc ? -3 : 0;

@@ -48,6 +48,15 @@ typedef struct {
     double w_min;               /* termination fraction of the launch luminosity */
     int64_t event_cap;          /* maximum scattering events per packet */
     double tau_peel_max;        /* peel-offs with optical depth >= this are dropped */
+    /* learned direction proposal (NULL mlp = plain sampling) */
+    const double *mlp;          /* 7400 parameters, weights bfloat16-representable */
+    double alpha;               /* weight of the physical component */
+    const double *lambda_um;    /* [n_lambda] wavelengths (features) */
+    /* derived by or_run: position feature scale (half the largest box side),
+     * (log lambda - log lambda_min) / log range, mean cell density */
+    double r_out;
+    const double *lam_feature;
+    double rho_mean;
 } or_scene;
 
 typedef struct {
@@ -75,6 +84,12 @@ typedef struct {
     double *table_m2;
     double *image_m2;
     or_stats stats;
+    /* optional plain-run histories: per packet (launch order) and event e <
+     * hist_events: 9 features, new direction (3), luminosity after the event,
+     * image flux produced so far; hist_total: the packet's total image flux */
+    double *hist;
+    double *hist_total;
+    int32_t hist_events;
 } or_out;
 
 /* Runs packet ids [first_id, first_id + count) of every wavelength, with the
@@ -100,6 +115,10 @@ double or_log(double x);
 double or_log1p(double x);
 double or_atanh(double x);
 void or_sincos(double x, double *s, double *c);
+
+/* The proposal network on bfloat16-rounded inputs and activations, FP64
+ * sums: f[9] -> out[40]. */
+void or_mlp_forward(const double *theta, const double f[9], double out[40]);
 
 /* Henyey-Greenstein phase function and sampler. */
 double or_hg_phase(double g, double mu);

@@ -326,6 +326,27 @@ def torus(max_depth: int = 9, torus_depth: int = 8, n_lambda: int = 32, npix: in
 
 
 # ----------------------------------------------------------------------------
+# Initial weights of the direction-proposal network
+# ----------------------------------------------------------------------------
+
+MLP_SHAPES = [(9, 64), (64,), (64, 64), (64,), (64, 40), (40,)]
+
+
+def init_mlp(seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Seeded fan-in uniform initial parameters (float32, flat: W1 [9][64],
+    b1, W2 [64][64], b2, W3 [64][40], b3), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            bound = scale * math.sqrt(6.0 / shape[0])
+            parts.append(rng.uniform(-bound, bound, shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
 # Batch of small models
 # ----------------------------------------------------------------------------
 

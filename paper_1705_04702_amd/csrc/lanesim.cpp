@@ -65,6 +65,9 @@ typedef struct {
     int32_t precision;        // 0 FP32, 1 FP64
     int32_t top_level;        // -1 default
     uint32_t model;           // fourth word of the Philox counter
+    const double *lambda_um;  // wavelengths (learned features), may be NULL
+    const double *mlp;        // network parameters (bf16 weights) or NULL: plain sampling
+    double alpha;             // weight of the physical distribution in the proposal
 } ls_scene;
 
 typedef struct {
@@ -72,6 +75,9 @@ typedef struct {
     double *images;  // concatenated [n_lambda][ny][nx] per instrument, flux
     double *energy;  // [4]
     uint64_t *stats; // [9]
+    double *hist;       // [packets][hist_events][14] or NULL
+    double *hist_total; // [packets]
+    int32_t hist_events;
 } ls_out;
 
 }
@@ -121,8 +127,12 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     v.n_cells = s->n_cells;
     v.n_lambda = s->n_lambda;
     std::vector<Optics<Real>> optics((size_t)s->n_lambda);
+    double r_out = 0.0, rho_mean = 0.0;
+    std::vector<double> lamf;
+    feature_constants(s->box, s->density, s->n_cells, s->lambda_um, s->n_lambda, r_out, rho_mean, lamf);
     for (int l = 0; l < s->n_lambda; ++l)
-        optics[l] = Optics<Real>{(Real)s->kappa[l], (Real)s->albedo[l], (Real)s->g[l], (Real)(s->L[l] / (double)npl)};
+        optics[l] = Optics<Real>{(Real)s->kappa[l], (Real)s->albedo[l], (Real)s->g[l], (Real)(s->L[l] / (double)npl),
+                                 (Real)lamf[l]};
     v.optics = optics.data();
     v.src_type = s->src_type;
     for (int a = 0; a < 3; ++a) v.src_pos[a] = (Real)s->src_pos[a];
@@ -150,15 +160,37 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     v.key0 = (uint32_t)(seed & 0xffffffffu);
     v.key1 = (uint32_t)(seed >> 32);
     v.model = s->model;
+    v.learned = s->mlp != nullptr;
+    v.alpha = (Real)s->alpha;
+    std::vector<double> mlp64;
+    if (s->mlp) {
+        std::vector<float> theta(s->mlp, s->mlp + kMlpParams); // FP32 master values
+        mlp_params_f64(theta.data(), mlp64);
+        v.mlp64 = mlp64.data();
+    }
+    v.r_out = (Real)r_out;
+    v.rho_mean = (Real)rho_mean;
+    std::vector<Real> hist, hist_total;
+    if (o->hist && !s->mlp) {
+        hist.assign((size_t)count * s->n_lambda * o->hist_events * kHistFloats, Real(0));
+        hist_total.assign((size_t)count * s->n_lambda, Real(0));
+        v.hist = hist.data();
+        v.hist_total = hist_total.data();
+        v.hist_events = o->hist_events;
+    }
 
     HostSink sink;
     Tally ty{};
     for (int l = 0; l < s->n_lambda; ++l) {
         for (uint64_t i = first; i < first + count; ++i) {
             Lane<Real> ln{};
-            launch(v, ln, ty, (uint32_t)l, (uint32_t)i);
+            launch(v, ln, ty, (uint32_t)l, (uint32_t)i, (uint32_t)((uint64_t)l * count + (i - first)));
             settle(v, ln, ty, sink);
             while (ln.mode != kDead) {
+                if (ln.mode == kNeedDir) {
+                    resolve_direction_scalar(v, ln, ty, sink);
+                    continue;
+                }
                 march_step(v, ln, ty, sink);
                 if (!ln.marching) settle(v, ln, ty, sink);
             }
@@ -183,6 +215,8 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     uint64_t st[9] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells, ty.peel_cells,
                       ty.peel_adds, ty.peel_dropped, ty.capped, ty.guard};
     std::memcpy(o->stats, st, sizeof(st));
+    for (size_t q = 0; q < hist.size(); ++q) o->hist[q] = (double)hist[q];
+    for (size_t q = 0; q < hist_total.size(); ++q) o->hist_total[q] = (double)hist_total[q];
     return 0;
 }
 
@@ -190,6 +224,8 @@ extern "C" int ls_run(const ls_scene *s, uint64_t n_per_lambda, uint64_t first_i
                       ls_out *out)
 {
     if (!s || !out || n_per_lambda == 0 || first_id + count > n_per_lambda) return -1;
+    if (s->mlp && !s->lambda_um) return -1;
+    if (out->hist && (!out->hist_total || out->hist_events < 1)) return -1;
     if (s->grid_type == kOctree) {
         if (s->precision == 1) return run<double, kOctree>(s, n_per_lambda, first_id, count, seed, out);
         return run<float, kOctree>(s, n_per_lambda, first_id, count, seed, out);

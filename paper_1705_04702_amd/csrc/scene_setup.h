@@ -40,6 +40,47 @@ inline void make_ins_desc(const HostInstrument &h, long long offset, InsDesc<Rea
     o.ny = h.npix[1];
     o.offset = offset;
     inv4pid2 = 1.0 / (4.0 * pi * h.distance * h.distance);
+    o.inv4pid2 = (Real)inv4pid2;
+}
+
+// Parameters of the proposal network as the FP64 scalar network reads them:
+// FP32 master values, weights rounded to bfloat16 (nearest even), biases kept.
+// Layout: W1 [9][64], b1 [64], W2 [64][64], b2 [64], W3 [64][40], b3 [40].
+inline void mlp_params_f64(const float *theta, std::vector<double> &out)
+{
+    out.assign((size_t)kMlpParams, 0.0);
+    const int w1 = 0, b1 = 9 * 64, w2 = b1 + 64, b2 = w2 + 64 * 64, w3 = b2 + 64, b3 = w3 + 64 * 40;
+    for (int i = 0; i < kMlpParams; ++i) {
+        bool weight = (i < b1) || (i >= w2 && i < b2) || (i >= w3 && i < b3);
+        out[(size_t)i] = weight ? (double)Bf16<float>::round(theta[i]) : (double)theta[i];
+    }
+    (void)w1;
+}
+
+// Constants of the learned proposal's features: r_out = half the largest box
+// side, the mean cell density (sequential FP64 sum in cell order) and, per
+// wavelength, (log l - log l_min) / (log l_max - log l_min), 0 for a single
+// wavelength.
+inline void feature_constants(const double box[6], const float *density, long long n_cells,
+                              const double *lambda_um, int n_lambda, double &r_out, double &rho_mean,
+                              std::vector<double> &lamf)
+{
+    double side = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (box[3 + a] - box[a] > side) side = box[3 + a] - box[a];
+    r_out = 0.5 * side;
+    double sum = 0.0;
+    for (long long m = 0; m < n_cells; ++m) sum = sum + (double)density[m];
+    rho_mean = sum / (double)n_cells;
+    lamf.assign((size_t)n_lambda, 0.0);
+    if (!lambda_um || n_lambda <= 0) return;
+    double lmin = lambda_um[0], lmax = lambda_um[0];
+    for (int l = 1; l < n_lambda; ++l) {
+        if (lambda_um[l] < lmin) lmin = lambda_um[l];
+        if (lambda_um[l] > lmax) lmax = lambda_um[l];
+    }
+    for (int l = 0; l < n_lambda; ++l)
+        lamf[l] = lmax > lmin ? (std::log(lambda_um[l]) - std::log(lmin)) / (std::log(lmax) - std::log(lmin)) : 0.0;
 }
 
 // Encodes an octree given as first_child (-1 for leaves, children contiguous

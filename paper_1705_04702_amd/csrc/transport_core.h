@@ -31,7 +31,11 @@ enum Mode : int {
     kLocate = 3,    // second march to the forced interaction point
     kPeelScat = 4,  // scattering peel-off march towards instrument j
     kLaunched = 5,  // launched, first march not yet begun
+    kNeedDir = 6,   // waiting for the learned proposal to pick the next direction
 };
+
+constexpr int kMlpParams = 7400; // 9 -> 64 -> 64 -> 40
+constexpr int kHistFloats = 14;  // features (9), new direction (3), luminosity, flux so far
 
 enum GridType : int { kCartesian = 0, kOctree = 1 };
 enum SourceType : int { kPointIso = 0, kPointAniso = 1, kExpDisk = 2 };
@@ -104,10 +108,11 @@ template <typename Real> struct InsDesc {
     Real half_fovx, half_fovy, pixx, pixy; // pixel size = fov / npix
     int nx, ny;
     long long offset; // first image element of this instrument
+    Real inv4pid2;    // flux per unit of image accumulation
 };
 
 template <typename Real> struct Optics {
-    Real kappa, albedo, g, L0;
+    Real kappa, albedo, g, L0, lamf; // lamf: wavelength feature of the proposal
 };
 
 template <typename Real, typename ImgT, int G> struct View {
@@ -143,6 +148,15 @@ template <typename Real, typename ImgT, int G> struct View {
     Real tau_peel_max;
     int octree_guard;
     uint32_t key0, key1, model;
+    // learned proposal (learned = 0: plain sampling)
+    int learned;
+    Real alpha;
+    const double *mlp64;  // FP64 copy of the parameters (bf16 values) for the scalar network
+    Real r_out, rho_mean; // feature scales
+    // plain-run histories (hist == nullptr: not recorded)
+    Real *hist;           // [slot][hist_events][kHistFloats]
+    Real *hist_total;     // [slot]
+    int hist_events;
 };
 
 // Per-lane tallies, reduced once per wave at the end of the kernel.
@@ -165,7 +179,10 @@ template <typename Real> struct Lane {
     int mode, j, nseg, steps;
     long long e;
     uint32_t id, lam;
-    bool marching, found, dropped;
+    uint32_t slot;      // packet index in the launch (histories)
+    Real rho_star;      // density of the interaction cell
+    Real flux;          // image flux produced so far (histories)
+    bool marching, found, dropped, emis_dir;
 };
 
 // Per-axis fields are separate scalars (not arrays): stores through a
@@ -461,6 +478,7 @@ MCRT_HD bool apply_segment(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &
             ln.a_tau = tprev;
             ln.a_kr = kr;
             ln.a_ds = ds;
+            ln.rho_star = (Real)rho;
         }
         if (ln.tau >= ln.tau_int) {
             ln.found = true;
@@ -625,33 +643,263 @@ MCRT_HD void begin_locate(const View<Real, ImgT, G> &v, Lane<Real> &ln)
     begin_march(v, ln, ln.k);
 }
 
-// Scattering: new HG direction, then the next propagation (or the event cap).
+// ---------------------------------------------------------------------------
+// Learned direction proposal and plain-run histories
+// ---------------------------------------------------------------------------
+template <typename Real> struct Bf16;
+template <> struct Bf16<float> {
+    // nearest-even rounding to bfloat16, returned as float
+    MCRT_HD static float round(float x)
+    {
+        uint32_t b;
+        __builtin_memcpy(&b, &x, sizeof b);
+        b = ((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16) << 16;
+        float r;
+        __builtin_memcpy(&r, &b, sizeof r);
+        return r;
+    }
+};
+template <> struct Bf16<double> {
+    MCRT_HD static double round(double x) { return (double)Bf16<float>::round((float)x); }
+};
+
+// Packet end: the total image flux of the packet goes to the histories.
+template <typename Real, typename ImgT, int G>
+MCRT_HD void end_packet(const View<Real, ImgT, G> &v, Lane<Real> &ln)
+{
+    ln.mode = kDead;
+    ln.marching = false;
+    if (v.hist) v.hist_total[ln.slot] = ln.flux;
+}
+
+// Features: position / r_out, incoming direction (zero at emission), the
+// wavelength feature, log10 of the interaction cell's density over the mean
+// (zero at emission), event flag.
+template <typename Real, typename ImgT, int G>
+MCRT_HD void event_features(const View<Real, ImgT, G> &v, const Lane<Real> &ln, bool scattering, Real f[9])
+{
+    const Real inv_ln10 = Real(0.43429448190325182765);
+    for (int a = 0; a < 3; ++a) f[a] = ln.r[a] / v.r_out;
+    for (int a = 0; a < 3; ++a) f[3 + a] = scattering ? ln.k[a] : Real(0);
+    f[6] = ln.opt.lamf;
+    f[7] = scattering ? Math<Real>::e_log(ln.rho_star / v.rho_mean) * inv_ln10 : Real(0);
+    f[8] = scattering ? Real(1) : Real(0);
+}
+
+template <typename Real, typename ImgT, int G>
+MCRT_HD void record_event(const View<Real, ImgT, G> &v, const Lane<Real> &ln, long long e, const Real f[9],
+                          const Real kp[3], Real L)
+{
+    if (!v.hist || e >= v.hist_events) return;
+    Real *h = v.hist + ((long long)ln.slot * v.hist_events + e) * kHistFloats;
+    for (int i = 0; i < 9; ++i) h[i] = f[i];
+    for (int i = 0; i < 3; ++i) h[9 + i] = kp[i];
+    h[12] = L;
+    h[13] = ln.flux;
+}
+
+// The proposal network one sample at a time: bf16-rounded inputs and hidden
+// activations, sums over the inputs in order, then the bias.
+template <typename Real>
+MCRT_HD void mlp_forward_scalar(const double *theta, const Real f[9], Real out[40])
+{
+    const double *W1 = theta, *b1 = W1 + 9 * 64, *W2 = b1 + 64, *b2 = W2 + 64 * 64;
+    const double *W3 = b2 + 64, *b3 = W3 + 64 * 40;
+    Real x[9], h1[64], h2[64];
+    for (int k = 0; k < 9; ++k) x[k] = Bf16<Real>::round(f[k]);
+    for (int j = 0; j < 64; ++j) {
+        Real acc = Real(0);
+        for (int k = 0; k < 9; ++k) acc = acc + x[k] * (Real)W1[k * 64 + j];
+        Real z = acc + (Real)b1[j];
+        h1[j] = Bf16<Real>::round(z > Real(0) ? z : Real(0));
+    }
+    for (int j = 0; j < 64; ++j) {
+        Real acc = Real(0);
+        for (int k = 0; k < 64; ++k) acc = acc + h1[k] * (Real)W2[k * 64 + j];
+        Real z = acc + (Real)b2[j];
+        h2[j] = Bf16<Real>::round(z > Real(0) ? z : Real(0));
+    }
+    for (int j = 0; j < 40; ++j) {
+        Real acc = Real(0);
+        for (int k = 0; k < 64; ++k) acc = acc + h2[k] * (Real)W3[k * 40 + j];
+        out[j] = acc + (Real)b3[j];
+    }
+}
+
+template <typename Real> struct Consts4 {
+    MCRT_HD static Real four_pi() { return Real(12.566370614359172953850573533118); }
+};
+
+// Direction from the proposal q = alpha p_phys + (1 - alpha) sum_j pi_j vMF_j
+// given the network outputs; the packet carries W = p_phys / q.  Then the
+// next propagation (after a scattering: the event count and cap first).
+template <typename Real, typename ImgT, int G>
+MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, const Real o[40])
+{
+    Real pi[8], mu[8][3], kap[8];
+    Real mx = o[0];
+    for (int j = 1; j < 8; ++j)
+        if (o[j] > mx) mx = o[j];
+    Real sum = Real(0);
+    for (int j = 0; j < 8; ++j) {
+        pi[j] = Math<Real>::e_exp(o[j] - mx);
+        sum = sum + pi[j];
+    }
+    for (int j = 0; j < 8; ++j) {
+        pi[j] = pi[j] / sum;
+        Real a = o[8 + 3 * j], b = o[9 + 3 * j], c = o[10 + 3 * j];
+        Real nrm = sqrt(a * a + b * b + c * c);
+        if (nrm > Real(0)) {
+            mu[j][0] = a / nrm;
+            mu[j][1] = b / nrm;
+            mu[j][2] = c / nrm;
+        } else {
+            mu[j][0] = Real(0);
+            mu[j][1] = Real(0);
+            mu[j][2] = Real(1);
+        }
+        Real sj = o[32 + j];
+        Real sp = Math<Real>::e_log1p(Math<Real>::e_exp(-fabs(sj))) + (sj > Real(0) ? sj : Real(0));
+        Real k = sp + Real(1e-3);
+        if (k < Real(1e-3)) k = Real(1e-3);
+        if (k > Real(1e3)) k = Real(1e3);
+        kap[j] = k;
+    }
+    Stream st = stream_of(v, ln);
+    const bool emis = ln.emis_dir;
+    Real u1 = st.template slot<Real>(emis ? 5u : (uint32_t)(8 * ln.e + 1));
+    Real u2 = st.template slot<Real>(emis ? 6u : (uint32_t)(8 * ln.e + 2));
+    Real u3 = st.template slot<Real>(emis ? 7u : (uint32_t)(8 * ln.e + 3));
+    Real kp[3];
+    if (u3 < v.alpha) {
+        if (emis) {
+            Real m;
+            if (v.src_type == kPointAniso) m = u1 < Real(0.5) ? sqrt(Real(2) * u1) : -sqrt(Real(2) * u1 - Real(1));
+            else m = Real(2) * u1 - Real(1);
+            Real phi = Consts<Real>::two_pi() * u2;
+            Real s = sqrt(rmax(Real(0), Real(1) - m * m));
+            Real sphi, cphi;
+            Math<Real>::e_sincos(phi, sphi, cphi);
+            kp[0] = s * cphi;
+            kp[1] = s * sphi;
+            kp[2] = m;
+        } else {
+            kp[0] = ln.k[0];
+            kp[1] = ln.k[1];
+            kp[2] = ln.k[2];
+            rotate(kp, hg_sample(ln.opt.g, u1), Consts<Real>::two_pi() * u2);
+        }
+    } else {
+        Real w = (u3 - v.alpha) / (Real(1) - v.alpha), c = Real(0);
+        int j = 7;
+        for (int i = 0; i < 8; ++i) {
+            c = c + pi[i];
+            if (w < c) {
+                j = i;
+                break;
+            }
+        }
+        Real kj = kap[j];
+        Real cw = Real(1) + Math<Real>::e_log(u1 + (Real(1) - u1) * Math<Real>::e_exp(Real(-2) * kj)) / kj;
+        if (cw < Real(-1)) cw = Real(-1);
+        if (cw > Real(1)) cw = Real(1);
+        kp[0] = mu[j][0];
+        kp[1] = mu[j][1];
+        kp[2] = mu[j][2];
+        rotate(kp, cw, Consts<Real>::two_pi() * u2);
+    }
+    Real pphys;
+    if (emis) {
+        Real S = v.src_type == kPointAniso ? Real(2) * fabs(kp[2]) : Real(1);
+        pphys = S / Consts4<Real>::four_pi();
+    } else {
+        Real cosang = ln.k[0] * kp[0] + ln.k[1] * kp[1] + ln.k[2] * kp[2];
+        pphys = hg_phase(ln.opt.g, cosang) / Consts4<Real>::four_pi();
+    }
+    Real qv = Real(0);
+    for (int j = 0; j < 8; ++j) {
+        Real kj = kap[j];
+        Real dot = mu[j][0] * kp[0] + mu[j][1] * kp[1] + mu[j][2] * kp[2];
+        Real fj = kj / (Consts<Real>::two_pi() * -Math<Real>::e_expm1(Real(-2) * kj)) *
+                  Math<Real>::e_exp(kj * (dot - Real(1)));
+        qv = qv + pi[j] * fj;
+    }
+    Real q = v.alpha * pphys + (Real(1) - v.alpha) * qv;
+    ln.L = (emis ? ln.L0 : ln.L) * (pphys / q);
+    ln.k[0] = kp[0];
+    ln.k[1] = kp[1];
+    ln.k[2] = kp[2];
+    if (!emis) {
+        ln.e = ln.e + 1;
+        if (ln.e > v.event_cap) {
+            ty.truncated += (double)ln.L;
+            ty.capped++;
+            end_packet(v, ln);
+            return;
+        }
+    }
+    begin_prop(v, ln);
+}
+
+// Scattering: new HG direction (or the learned proposal), then the next
+// propagation (or the event cap).
 template <typename Real, typename ImgT, int G>
 MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 {
+    if (v.learned) {
+        ln.mode = kNeedDir;
+        ln.emis_dir = false;
+        ln.marching = false;
+        return;
+    }
+    Real f[9];
+    if (v.hist) event_features(v, ln, true, f);
     Stream st = stream_of(v, ln);
     Real u1 = st.template slot<Real>((uint32_t)(8 * ln.e + 1));
     Real u2 = st.template slot<Real>((uint32_t)(8 * ln.e + 2));
     Real mu = hg_sample(ln.opt.g, u1);
     Real phi = Consts<Real>::two_pi() * u2;
     rotate(ln.k, mu, phi);
+    if (v.hist) record_event(v, ln, ln.e, f, ln.k, ln.L);
     ln.e = ln.e + 1;
     if (ln.e > v.event_cap) {
         ty.truncated += (double)ln.L;
         ty.capped++;
-        ln.mode = kDead;
+        end_packet(v, ln);
+        return;
+    }
+    begin_prop(v, ln);
+}
+
+// After the emission peel-offs: the emission direction (already sampled, or
+// left to the learned proposal for point sources), then the first propagation.
+template <typename Real, typename ImgT, int G>
+MCRT_HD void emission_done(const View<Real, ImgT, G> &v, Lane<Real> &ln)
+{
+    if (v.learned && v.src_type != kExpDisk) {
+        ln.mode = kNeedDir;
+        ln.emis_dir = true;
         ln.marching = false;
         return;
+    }
+    if (v.hist) {
+        Real f[9];
+        event_features(v, ln, false, f);
+        record_event(v, ln, 0, f, ln.k, ln.L0);
     }
     begin_prop(v, ln);
 }
 
 // Launches packet (lam, id): position, direction, emission peel-offs.
 template <typename Real, typename ImgT, int G>
-MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id)
+MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id,
+                    uint32_t slot)
 {
     ln.lam = lam;
     ln.id = id;
+    ln.slot = slot;
+    ln.flux = Real(0);
+    ln.emis_dir = false;
     ln.opt = v.optics[lam];
     Stream st = stream_of(v, ln);
     if (v.src_type == kExpDisk) {
@@ -671,19 +919,21 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
         ln.r[1] = v.src_pos[1];
         ln.r[2] = v.src_pos[2];
     }
-    Real u4, u5, u6, u7;
-    st.template pair<Real>(2, u4, u5);
-    st.template pair<Real>(3, u6, u7);
-    Real mu;
-    if (v.src_type == kPointAniso) mu = u5 < Real(0.5) ? sqrt(Real(2) * u5) : -sqrt(Real(2) * u5 - Real(1));
-    else mu = Real(2) * u5 - Real(1);
-    Real phi = Consts<Real>::two_pi() * u6;
-    Real s = sqrt(rmax(Real(0), Real(1) - mu * mu));
-    Real sphi, cphi;
-    Math<Real>::e_sincos(phi, sphi, cphi);
-    ln.k[0] = s * cphi;
-    ln.k[1] = s * sphi;
-    ln.k[2] = mu;
+    if (!(v.learned && v.src_type != kExpDisk)) {
+        Real u4, u5, u6, u7;
+        st.template pair<Real>(2, u4, u5);
+        st.template pair<Real>(3, u6, u7);
+        Real mu;
+        if (v.src_type == kPointAniso) mu = u5 < Real(0.5) ? sqrt(Real(2) * u5) : -sqrt(Real(2) * u5 - Real(1));
+        else mu = Real(2) * u5 - Real(1);
+        Real phi = Consts<Real>::two_pi() * u6;
+        Real s = sqrt(rmax(Real(0), Real(1) - mu * mu));
+        Real sphi, cphi;
+        Math<Real>::e_sincos(phi, sphi, cphi);
+        ln.k[0] = s * cphi;
+        ln.k[1] = s * sphi;
+        ln.k[2] = mu;
+    }
     ln.L0 = ln.opt.L0;
     ln.L = ln.L0;
     ln.e = 1;
@@ -693,13 +943,14 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.marching = false;
 }
 
-// Handles the end of a march; leaves the lane marching again or dead.
+// Handles the end of a march; leaves the lane marching again, dead, or
+// waiting for the learned proposal.
 template <typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
     if (ln.mode == kLaunched) {
         if (v.n_ins > 0) begin_peel(v, ln, 0, true);
-        else begin_prop(v, ln);
+        else emission_done(v, ln);
         return;
     }
     if (ln.mode == kPeelEmit || ln.mode == kPeelScat) {
@@ -713,7 +964,9 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
             Real py = floor((y + in.half_fovy) / in.pixy);
             if (px >= Real(0) && px < Real(in.nx) && py >= Real(0) && py < Real(in.ny)) {
                 long long idx = in.offset + ((long long)ln.lam * in.ny + (long long)py) * in.nx + (long long)px;
-                sink.pixel(v.images + idx, (ImgT)(ln.wpeel * Math<Real>::e_exp(-ln.tau)));
+                Real val = ln.wpeel * Math<Real>::e_exp(-ln.tau);
+                sink.pixel(v.images + idx, (ImgT)val);
+                if (v.hist) ln.flux = ln.flux + val * in.inv4pid2;
                 ty.peel_adds++;
             }
         }
@@ -722,7 +975,7 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         if (j < v.n_ins) {
             begin_peel(v, ln, j, emission);
         } else if (emission) {
-            begin_prop(v, ln);
+            emission_done(v, ln);
         } else {
             scatter(v, ln, ty);
         }
@@ -732,13 +985,13 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         const Real Epath = ln.E;
         ty.escaped += (double)(ln.L * Epath);
         if (ln.nseg == 0 || ln.opt.albedo == Real(0) || ln.tau == Real(0)) {
-            ln.mode = kDead;
+            end_packet(v, ln);
             return;
         }
         Real Ls = ln.opt.albedo * ln.L * (Real(1) - Epath);
         if (Ls < v.w_min * ln.L0) {
             ty.truncated += (double)Ls;
-            ln.mode = kDead;
+            end_packet(v, ln);
             return;
         }
         Stream st = stream_of(v, ln);
@@ -761,13 +1014,25 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         else scatter(v, ln, ty);
         return;
     }
-    ln.mode = kDead;
+    end_packet(v, ln);
 }
 
 template <typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void settle(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
-    while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
+    while (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) finish_march(v, ln, ty, sink);
+}
+
+// One sample at a time: features, network, proposal (host simulator and the
+// FP64 validation kernel; the FP32 kernel evaluates the network per wave).
+template <typename Real, typename ImgT, int G, typename Sink>
+MCRT_HD void resolve_direction_scalar(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+{
+    Real f[9], o[40];
+    event_features(v, ln, !ln.emis_dir, f);
+    mlp_forward_scalar(v.mlp64, f, o);
+    apply_proposal(v, ln, ty, o);
+    settle(v, ln, ty, sink);
 }
 
 } // namespace mcrt

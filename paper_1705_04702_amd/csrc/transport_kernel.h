@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
                 uint64_t P = cur + rank;
                 uint32_t lam = (uint32_t)(P / a.count);
                 uint32_t id = (uint32_t)(a.first_id + P % a.count);
-                launch(v, ln, ty, lam, id);
+                launch(v, ln, ty, lam, id, (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
             uint32_t rank = lanes_below(dead);
             if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
-                launch(v, ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count));
+                launch(v, ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);

@@ -24,12 +24,16 @@ class _Scene(ctypes.Structure):
         ("ins_npix", ctypes.POINTER(ctypes.c_int32)), ("w_min", ctypes.c_double),
         ("event_cap", ctypes.c_int64), ("tau_peel_max", ctypes.c_double),
         ("precision", ctypes.c_int32), ("top_level", ctypes.c_int32), ("model", ctypes.c_uint32),
+        ("lambda_um", ctypes.POINTER(ctypes.c_double)), ("mlp", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.c_double),
     ]
 
 
 class _Out(ctypes.Structure):
     _fields_ = [("table", ctypes.POINTER(ctypes.c_double)), ("images", ctypes.POINTER(ctypes.c_double)),
-                ("energy", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.POINTER(ctypes.c_uint64))]
+                ("energy", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.POINTER(ctypes.c_uint64)),
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_total", ctypes.POINTER(ctypes.c_double)),
+                ("hist_events", ctypes.c_int32)]
 
 
 STATS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
@@ -51,7 +55,11 @@ def lib():
     return _lib
 
 
-def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level=-1, model=0):
+def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level=-1, model=0,
+        mlp=None, alpha=0.2, histories=0):
+    """mlp: FP32 network parameters (the simulator rounds the weights to
+    bf16 as the library does); histories: events recorded per packet (plain
+    runs)."""
     if count is None:
         count = n_per_lambda - first_id
     keep = []
@@ -92,6 +100,10 @@ def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level
     s.precision = precision
     s.top_level = top_level
     s.model = model
+    s.lambda_um = arr(sc.lambdas, np.float64, ctypes.c_double)
+    if mlp is not None:
+        s.mlp = arr(np.asarray(mlp, dtype=np.float32).astype(np.float64), np.float64, ctypes.c_double)
+    s.alpha = alpha
     nl = s.n_lambda
     table = np.zeros(s.n_cells * nl)
     shapes = [(nl, i.npix[1], i.npix[0]) for i in sc.instruments]
@@ -103,6 +115,13 @@ def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level
              images.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
              energy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
              stats.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    npk = count * nl
+    if histories:
+        hist = np.zeros(npk * histories * 14)
+        htot = np.zeros(npk)
+        o.hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.hist_total = htot.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.hist_events = histories
     rc = lib().ls_run(ctypes.byref(s), n_per_lambda, first_id, count, seed, ctypes.byref(o))
     if rc:
         raise RuntimeError(f"lanesim failed {rc}")
@@ -111,5 +130,9 @@ def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level
         n = int(np.prod(x))
         imgs.append(images[off:off + n].reshape(x))
         off += n
-    return {"table": table.reshape(s.n_cells, nl), "images": imgs, "energy": energy,
-            "stats": dict(zip(STATS, [int(x) for x in stats]))}
+    res = {"table": table.reshape(s.n_cells, nl), "images": imgs, "energy": energy,
+           "stats": dict(zip(STATS, [int(x) for x in stats]))}
+    if histories:
+        res["hist"] = hist.reshape(-1, histories, 14)
+        res["hist_total"] = htot
+    return res

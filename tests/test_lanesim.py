@@ -84,3 +84,52 @@ def test_model_index_enters_the_streams():
     np.testing.assert_array_equal(l["table"], o["table"])
     o0 = oracle.run(sc, 300, seed=3, model=0)
     assert not np.array_equal(o0["table"], o["table"])
+
+
+LEARNED_SCENES = {
+    "torus_aniso": (lambda: scenes.torus(5, 4, 3, 32, n_clumps=25, tau_eq=8.0), 150),
+    "sphere_iso": (lambda: scenes.sphere(n=12, tau=2.0, albedo=0.7), 400),
+    "disk": (lambda: scenes.disk((16, 16, 8), 3, 24), 120),
+}
+
+
+@pytest.mark.parametrize("name", list(LEARNED_SCENES))
+def test_learned_lane_logic_matches_oracle_fp64(name):
+    """Learned proposal (network, mixture, sampling, weights): the lane code
+    reproduces the oracle bit for bit in FP64 (point sources use the proposal
+    at emission too; the disk source keeps its physical emission)."""
+    make, N = LEARNED_SCENES[name]
+    sc = make()
+    theta = scenes.init_mlp(11, scale=1.5)
+    o = oracle.run(sc, N, seed=9, mlp=theta)
+    l = lanesim.run(sc, N, seed=9, precision=1, mlp=theta)
+    np.testing.assert_array_equal(l["table"], o["table"])
+    np.testing.assert_array_equal(l["energy"], o["energy"])
+    for a, b in zip(l["images"], o["images"]):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+    for k in ("packets", "events", "prop_cells", "peel_adds", "capped"):
+        assert l["stats"][k] == o["stats"][k], k
+
+
+def test_learned_lane_logic_fp32_statistical():
+    sc = scenes.sphere(n=12, tau=2.0, albedo=0.7)
+    theta = scenes.init_mlp(11, scale=1.5)
+    N = 3000
+    o = oracle.run(sc, N, seed=3, mlp=theta, moments=True)
+    l = lanesim.run(sc, N, seed=3, precision=0, mlp=theta)
+    T = o["table"]
+    sig = np.sqrt(max((o["table_m2"] - T * T / N).sum(), 0.0))
+    # the same random numbers: FP32 differs from FP64 by rounding only
+    assert abs(l["table"].sum() - T.sum()) <= 1e-3 * T.sum() + 3 * sig
+
+
+@pytest.mark.parametrize("name", ["torus_aniso", "disk"])
+def test_histories_match_oracle(name):
+    make, N = LEARNED_SCENES[name]
+    sc = make()
+    E = 10
+    o = oracle.run(sc, N, seed=5, histories=E, first_id=7, count=N - 20)
+    l = lanesim.run(sc, N, seed=5, precision=1, histories=E, first_id=7, count=N - 20)
+    np.testing.assert_array_equal(l["hist"], o["hist"])
+    np.testing.assert_array_equal(l["hist_total"], o["hist_total"])
+    np.testing.assert_array_equal(l["table"], o["table"])

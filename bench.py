@@ -119,6 +119,114 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _image_cube(res, n_ins):
+    import numpy as np
+    return np.concatenate([res.image(j).ravel() for j in range(n_ins)])
+
+
+def bench_learned(args):
+    """Learned direction proposal on the clumpy-torus workload: collect plain
+    histories (1e7 packets, seed 1), train the network (Adam, lr 1e-3), then
+    compare the image error of a learned run (1e8 packets, seed 2) with a
+    plain run of equal transport time (seed 3), both against a plain
+    reference of 1e9 packets (seed 4).  RMS = sqrt(sum (I - I_ref)^2) /
+    sqrt(sum I_ref^2) over all pixels and wavelengths, with the reference's
+    own noise (from its two halves) subtracted; figure of merit 1 / (RMS^2 t)
+    with t the transport time.  Collection and training are reported
+    separately."""
+    import numpy as np
+    import torch
+    from paper_1705_04702_amd import mcrt, scenes
+    sc = scenes.torus()
+    nl = sc.n_lambda
+    n_hist = args.hist_packets // nl
+    n_learn = args.learned_packets // nl
+    n_ref = args.ref_packets // nl
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    n_ins = len(sc.instruments)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    def log(msg):
+        print(f"[bench-learned] {msg}", file=sys.stderr, flush=True)
+
+    # 1. histories of plain packets
+    r_hist = sim.new_result()
+    hist, t_collect = timed(lambda: sim.collect(r_hist, n_hist, seed=1, max_events=args.max_events))
+    log(f"collected {hist.n_packets} packets, {hist.n_samples} samples in {t_collect:.2f} s")
+    r_hist.close()
+    # 2. training
+    prop = mcrt.Proposal(ctx, seed=7, init_scale=1.0)
+    loss0 = prop.eval(hist)
+    _, t_train = timed(lambda: prop.train(hist, epochs=args.epochs, batch=8192, lr=1e-3, seed=3))
+    loss1 = prop.eval(hist)
+    log(f"trained {args.epochs} epochs in {t_train:.2f} s: loss {loss0:.4f} -> {loss1:.4f}")
+    hist.close()
+
+    def run(n_per_lambda, seed, learned, first=0, count=None):
+        """Runs ids [first, first + count) in blocks; returns the image cube and
+        the summed kernel time."""
+        count = n_per_lambda - first if count is None else count
+        sim.set_proposal(prop if learned else None, 0.2)
+        res = sim.new_result()
+        block = 3_000_000
+        kms = 0.0
+        for b0 in range(first, first + count, block):
+            cnt = min(block, first + count - b0)
+            sim.run_into(res, n_per_lambda, seed=seed, first_id=b0, count=cnt)
+            kms = res.stats()["kernel_ms"] + kms
+            log(f"{'learned' if learned else 'plain'} ids [{b0}, {b0 + cnt}) of {n_per_lambda}/lambda done")
+        img = _image_cube(res, n_ins)
+        e = res.energy()
+        res.close()
+        return img, kms / 1e3, e
+
+    # 3. reference in two halves, learned run, plain run of equal transport time
+    half = n_ref // 2
+    ref_a, t_ra, _ = run(n_ref, 4, False, 0, half)
+    ref_b, t_rb, _ = run(n_ref, 4, False, half, n_ref - half)
+    ref = ref_a + ref_b
+    t_ref = t_ra + t_rb
+    learned, t_learned, e_learned = run(n_learn, 2, True)
+    plain_rate = n_ref * nl / t_ref
+    n_plain = max(1, int(plain_rate * t_learned / nl))
+    plain, t_plain, _ = run(n_plain, 3, False)
+    ref2 = float(np.sum(ref * ref))
+    noise = float(np.sum((ref_a - ref_b) ** 2))  # estimates the reference's own variance sum
+    rms_l = float(np.sqrt(max(np.sum((learned - ref) ** 2) - noise, 0.0) / ref2))
+    rms_p = float(np.sqrt(max(np.sum((plain - ref) ** 2) - noise, 0.0) / ref2))
+    fom_l = 1.0 / (rms_l ** 2 * t_learned)
+    fom_p = 1.0 / (rms_p ** 2 * t_plain)
+    tot_l, tot_p, tot_r = float(learned.sum()), float(plain.sum()), float(ref.sum())
+    log(f"rms learned {rms_l:.4e} ({t_learned:.2f} s), plain {rms_p:.4e} ({t_plain:.2f} s), "
+        f"gain {fom_l / fom_p:.3f}")
+    out = {"metric": METRIC, "value": n_learn * nl / t_learned, "unit": "packets/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": t_learned * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "config": {"workload": "clumpy AGN torus (octree ~2.2e6 leaves, 32 wavelengths, 1024^2 edge-on "
+                                  "instrument) with the learned vMF-mixture direction proposal",
+                      "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
+                      "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
+                      "alpha": 0.2, "epochs": args.epochs, "max_events": args.max_events},
+           "learned_vs_plain": {"rms_learned": rms_l, "rms_plain": rms_p, "t_learned_s": t_learned,
+                                "t_plain_s": t_plain, "rms2_t_learned": rms_l ** 2 * t_learned,
+                                "rms2_t_plain": rms_p ** 2 * t_plain, "fom_gain": fom_l / fom_p,
+                                "flux_learned_over_ref": tot_l / tot_r, "flux_plain_over_ref": tot_p / tot_r,
+                                "reference_noise_fraction": noise / ref2,
+                                "collect_s": t_collect, "train_s": t_train, "loss_before": loss0,
+                                "loss_after": loss1, "energy_balance_learned":
+                                    abs(e_learned[0] - e_learned[1] - e_learned[2] - e_learned[3]) / e_learned[0]}}
+    prop.close()
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle, one wavelength per task, tasks spread over
 # processes (replicated scene, per-process tables summed -- the paper's task
@@ -197,6 +305,11 @@ def main():
     ap.add_argument("--brick", default="", help="log2 brick sizes, e.g. 1,0,4")
     ap.add_argument("--microbench", action="store_true",
                     help="only print the memory-system microbenchmarks (one JSON line)")
+    ap.add_argument("--hist-packets", type=int, default=10_000_000, help="torus-learned: history packets")
+    ap.add_argument("--learned-packets", type=int, default=100_000_000, help="torus-learned: learned packets")
+    ap.add_argument("--ref-packets", type=int, default=1_000_000_000, help="torus-learned: reference packets")
+    ap.add_argument("--epochs", type=int, default=2, help="torus-learned: training epochs")
+    ap.add_argument("--max-events", type=int, default=16, help="torus-learned: recorded events per packet")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +337,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "torus-learned":
+        bench_learned(args)
         return
     scene, workload = make_scene(args.workload)
     N = args.n_per_lambda or WORKLOADS[args.workload][0]

@@ -66,6 +66,8 @@ typedef struct mcrt_source mcrt_source;
 typedef struct mcrt_instrument mcrt_instrument;
 typedef struct mcrt_sim mcrt_sim;
 typedef struct mcrt_result mcrt_result;
+typedef struct mcrt_proposal mcrt_proposal;
+typedef struct mcrt_histories mcrt_histories;
 
 typedef struct {
     int32_t precision;     /* MCRT_FP32 or MCRT_FP64_VALIDATE */
@@ -204,6 +206,98 @@ int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
  * additions. */
 int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packets, uint64_t seed,
                   const char *cache_path, mcrt_tuning *best);
+
+/* ------------------------------------------------------------------------
+ * Learned direction proposal.  An extension of the interaction-direction
+ * sampling of Section 3.2 (the paper itself samples directions from the
+ * physical phase function): a small network maps the features of an
+ * emission or scattering event -- position / r_out (r_out = half the largest
+ * box side), incoming direction (zero at emission), the wavelength feature
+ * (log l - log l_min) / (log l_max - log l_min), log10 of the interaction
+ * cell's density over the mean cell density (zero at emission) and an event
+ * flag (0 emission, 1 scattering) -- to an 8-lobe von Mises-Fisher mixture.
+ * New directions are drawn from q = alpha p_phys + (1 - alpha) sum_j pi_j
+ * vMF_j and the packet luminosity is multiplied by p_phys / q, so every
+ * tally keeps its expectation.  Point sources use the proposal at emission
+ * too; the disk source keeps its physical emission.
+ * Network: 9 -> 64 -> 64 -> 40 with ReLU, outputs = 8 mixture logits, 8 x 3
+ * raw lobe axes (normalised), 8 raw concentrations (kappa = clamp(softplus +
+ * 1e-3, 1e-3, 1e3)).  Weights, inputs and hidden activations are bfloat16
+ * (nearest even); sums FP32 on the matrix cores (FP64 in the FP64
+ * validation transport).  Parameter layout (7400 floats): W1 [9][64]
+ * (input-major), b1 [64], W2 [64][64], b2 [64], W3 [64][40], b3 [40].
+ * ---------------------------------------------------------------------- */
+#define MCRT_MLP_PARAMS 7400
+
+typedef struct {
+    int32_t n_in, n_hidden, n_out; /* must be 9, 64, 40 */
+    uint64_t init_seed;            /* uniform fan-in initialisation, biases 0 */
+    float init_scale;              /* weights U(-b, b), b = init_scale sqrt(6 / fan_in) */
+} mcrt_mlp_desc;
+
+int mcrt_proposal_create(mcrt_context *ctx, const mcrt_mlp_desc *desc, mcrt_proposal **out);
+void mcrt_proposal_destroy(mcrt_proposal *p);
+/* FP32 master parameters (host or device buffers, count = 7400); setting them
+ * also resets the Adam state.  get_weights: the parameters rounded to
+ * bfloat16 bit patterns (as the network uses the weights). */
+int mcrt_proposal_set_params(mcrt_proposal *p, const float *theta, size_t count);
+int mcrt_proposal_get_params(const mcrt_proposal *p, float *theta, size_t count);
+int mcrt_proposal_get_weights(const mcrt_proposal *p, uint16_t *bf16, size_t count);
+/* Network outputs on the matrix cores: X [n][9] -> out [n][40] (host or
+ * device buffers). */
+int mcrt_proposal_forward(mcrt_proposal *p, const float *X, int64_t n, float *out);
+/* Weighted negative log-likelihood of the vMF part,
+ * loss = -sum_e C_e log q_vMF(KP_e | X_e) / sum_e C_e, and its gradient
+ * [7400] in the parameter layout, for n samples (features X [n][9],
+ * directions KP [n][3], weights C [n] >= 0, not all zero; host or device
+ * buffers).  The backward pass carries the output and pre-activation
+ * gradients as bfloat16 high + low parts on the matrix cores. */
+int mcrt_proposal_grad(mcrt_proposal *p, const float *X, const float *KP, const float *C, int64_t n,
+                       double *loss, float *grad);
+
+/* Attaches the proposal to a sim (p = NULL detaches).  alpha in (0, 1] is
+ * the weight of the physical distribution (defensive mixture).  The medium
+ * must have been created with wavelengths.  The proposal must outlive the
+ * sim's runs; batched runs reject sims with a proposal. */
+int mcrt_sim_set_proposal(mcrt_sim *sim, mcrt_proposal *p, double alpha);
+
+/* Plain run (no proposal attached) of packet ids [first_id, first_id +
+ * count) of every wavelength that ADDS to res like mcrt_run_into and also
+ * records, per packet (slot = wavelength * count + id - first_id) and per
+ * event e < max_events (e = 0 emission, e >= 1 scattering e): the 9
+ * features, the direction taken (3), the luminosity after the event and the
+ * image flux the packet had produced so far; plus each packet's total image
+ * flux.  Training samples are the recorded events with weight C = (total -
+ * flux so far) / luminosity > 0, in (slot, event) order.  At most 2^32
+ * packets.  Returns MCRT_ELIMIT with valid histories if a packet hit the
+ * event cap. */
+int mcrt_proposal_collect(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
+                          uint64_t seed, int32_t max_events, mcrt_result *res, mcrt_histories **out);
+int mcrt_histories_info(const mcrt_histories *h, int64_t *n_packets, int32_t *max_events,
+                        int64_t *n_samples, double *weight_sum);
+/* Raw records [packet][max_events][14] (zero for events not reached) and
+ * packet totals, converted to double (host or device buffers). */
+int mcrt_histories_records(const mcrt_histories *h, double *records, size_t count, double *totals,
+                           size_t count_totals);
+/* Training samples: X [n][9], KP [n][3], C [n] (host or device buffers). */
+int mcrt_histories_samples(const mcrt_histories *h, float *X, float *KP, float *C, size_t n);
+void mcrt_histories_destroy(mcrt_histories *h);
+
+typedef struct {
+    int32_t epochs;      /* passes over the samples (in minibatch draws) */
+    int32_t batch;       /* samples per Adam step, drawn uniformly with replacement */
+    float lr, beta1, beta2, eps;
+    uint64_t seed;       /* minibatch draws */
+} mcrt_train_opts;
+void mcrt_train_opts_default(mcrt_train_opts *opt);
+/* Adam on the FP32 master parameters for epochs * ceil(n_samples / batch)
+ * steps (forward and backward on the matrix cores); *final_loss (may be
+ * NULL) receives the last minibatch's loss.  The Adam state persists across
+ * calls until mcrt_proposal_set_params. */
+int mcrt_proposal_train(mcrt_proposal *p, const mcrt_histories *h, const mcrt_train_opts *opt,
+                        double *final_loss);
+/* Loss over all samples of h at the current parameters. */
+int mcrt_proposal_eval(mcrt_proposal *p, const mcrt_histories *h, double *loss);
 
 /* Absorbed luminosity table, out[i * n_lambda + j] for cell i and
  * wavelength j (Section 5.2, ParallelTable element (i, j)); count >=

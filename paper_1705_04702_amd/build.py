@@ -29,6 +29,7 @@ UNITS = [
     ("transport_f32.hip", ["-x", "hip"]),
     ("transport_f64.hip", ["-x", "hip", "-ffp-contract=off"]),
     ("aux_kernels.hip", ["-x", "hip"]),
+    ("proposal.hip", ["-x", "hip"]),
     ("microbench.hip", ["-x", "hip"]),
     ("mcrt_api.cpp", []),
 ]

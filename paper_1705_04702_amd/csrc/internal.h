@@ -26,6 +26,8 @@ template <typename Real, typename ImgT, int G> struct TransportArgs {
     unsigned long long *counter;  // queue position (chunks handed out)
     double *energy;               // [4] emitted, absorbed, escaped, truncated
     unsigned long long *stats;    // [kNumStats]
+    const void *mlp_frags;        // learned FP32: forward fragments (bf16, fragment order)
+    const float *mlp_bias;        // learned FP32: biases [176]
 };
 
 // G = 0 Cartesian, 1 octree
@@ -73,6 +75,42 @@ template <typename Real, typename ImgT> struct BatchArgs {
 };
 
 hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream);
+
+// learned proposal (proposal.hip)
+struct GradArgs {
+    const uint16_t *frags;    // all 60 fragments
+    const float *bias;        // [176]
+    const float *X, *KP, *C;  // samples: features [n][9], direction [n][3], weight [n]
+    int64_t n;                // samples available
+    int64_t m;                // samples in this pass
+    int random;               // 0: samples 0 .. m-1; 1: m uniform draws (with replacement) from [0, n)
+    uint32_t key0, key1, step;
+    float scale;              // multiplies every weight (1 / sum of the weights of the pass)
+    float *partial;           // [waves][kGradStride]
+    double *loss_partial;     // [waves]
+};
+struct AdamArgs {
+    float *theta, *m, *v;     // FP32 master parameters and moments [7400]
+    float lr, b1, b2, eps;
+    int step;                 // Adam time step (>= 1)
+    int update;               // 0: only sum the gradient
+    float *grad_out;          // optional [7400]: the summed gradient
+    double *loss_out;         // optional: the summed loss
+};
+constexpr int kGradStrideFloats = 7424;
+constexpr int kFragAllElems = 60 * 64 * 4; // bf16 values of all fragments
+hipError_t launch_sum_f32(const float *x, int64_t n, double *out, hipStream_t stream);
+hipError_t launch_proposal_pack(const float *theta, uint16_t *frags, float *bias, double *theta64,
+                                hipStream_t stream);
+hipError_t launch_proposal_forward(const uint16_t *frags, const float *bias, const float *X, int64_t n, float *out,
+                                   hipStream_t stream);
+hipError_t launch_proposal_grad(const GradArgs &g, int waves, hipStream_t stream);
+hipError_t launch_proposal_adam(const float *partial, int waves, const double *loss_partial, const AdamArgs &a,
+                                hipStream_t stream);
+hipError_t launch_hist_count(const void *h, const void *tot, bool fp64, int64_t n_slots, int E, uint32_t *count,
+                             uint64_t *offset, uint64_t *block_sums, uint64_t *total, hipStream_t st);
+hipError_t launch_hist_write(const void *h, const void *tot, bool fp64, int64_t n_slots, int E,
+                             const uint64_t *offset, float *X, float *KP, float *C, hipStream_t st);
 hipError_t launch_batch_f64(const BatchArgs<double, double> &a, int grid, hipStream_t stream);
 
 } // namespace mcrt

@@ -32,6 +32,7 @@ using namespace mcrt;
 
 namespace {
 struct HostSink {
+    static constexpr bool kLearn = true, kHist = true; // chosen at run time
     void deposit(double *p, double v)
     {
         if (v != 0.0) *p += v;
@@ -184,11 +185,12 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     for (int l = 0; l < s->n_lambda; ++l) {
         for (uint64_t i = first; i < first + count; ++i) {
             Lane<Real> ln{};
-            launch(v, ln, ty, (uint32_t)l, (uint32_t)i, (uint32_t)((uint64_t)l * count + (i - first)));
+            launch<HostSink>(v, ln, ty, (uint32_t)l, (uint32_t)i, (uint32_t)((uint64_t)l * count + (i - first)));
             settle(v, ln, ty, sink);
             while (ln.mode != kDead) {
                 if (ln.mode == kNeedDir) {
-                    resolve_direction_scalar(v, ln, ty, sink);
+                    resolve_direction_scalar<HostSink>(v, ln, ty);
+                    if (!ln.marching) settle(v, ln, ty, sink);
                     continue;
                 }
                 march_step(v, ln, ty, sink);

@@ -94,6 +94,7 @@ struct mcrt_medium {
     std::vector<float> density;
     int n_lambda = 0;
     std::vector<double> kappa, albedo, g;
+    std::vector<double> lambda_um; // empty when not given
 };
 
 struct mcrt_source {
@@ -129,6 +130,33 @@ struct mcrt_sim {
     void *d_optics = nullptr; // Optics<Real>[n_lambda], rewritten per run
     void *d_ins = nullptr;    // InsDesc<Real>[n_ins]
     std::atomic<int> busy{0};
+    // learned proposal
+    mcrt_proposal *prop = nullptr;
+    double alpha = 0.2;
+    double r_out = 0.0, rho_mean = 0.0; // feature scales
+    std::vector<double> lamf;            // wavelength feature per bin
+};
+
+struct mcrt_proposal {
+    mcrt_context *ctx = nullptr;
+    float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr; // FP32 master, Adam moments [7400]
+    uint16_t *d_frags = nullptr;  // bf16 fragments [60][64][4]
+    float *d_bias = nullptr;      // [176]
+    double *d_theta64 = nullptr;  // FP64 copy for the scalar network [7400]
+    int step = 0;                 // Adam time step
+    std::atomic<int> busy{0};
+};
+
+struct mcrt_histories {
+    mcrt_context *ctx = nullptr;
+    int fp64 = 0;
+    int64_t n_packets = 0;
+    int events = 0;
+    void *d_hist = nullptr;   // Real [n_packets][events][14]
+    void *d_total = nullptr;  // Real [n_packets]
+    int64_t n_samples = 0;
+    float *d_X = nullptr, *d_KP = nullptr, *d_C = nullptr;
+    double c_sum = 0.0;
 };
 
 struct mcrt_result {
@@ -234,7 +262,6 @@ void mcrt_grid_destroy(mcrt_grid *grid) { delete grid; }
 int mcrt_medium_create(mcrt_grid *grid, const float *density, int32_t n_lambda, const double *lambda_um,
                        const double *kappa, const double *albedo, const double *g, mcrt_medium **out)
 {
-    (void)lambda_um;
     if (!out) return fail(MCRT_EINVAL, "medium_create: out is NULL");
     *out = nullptr;
     if (!grid || !density || !kappa || !albedo || !g) return fail(MCRT_EINVAL, "medium_create: NULL argument");
@@ -254,6 +281,14 @@ int mcrt_medium_create(mcrt_grid *grid, const float *density, int32_t n_lambda, 
     m->kappa.assign(kappa, kappa + n_lambda);
     m->albedo.assign(albedo, albedo + n_lambda);
     m->g.assign(g, g + n_lambda);
+    if (lambda_um) {
+        for (int l = 0; l < n_lambda; ++l)
+            if (!(lambda_um[l] > 0.0) || !std::isfinite(lambda_um[l])) {
+                delete m;
+                return fail(MCRT_EINVAL, "medium_create: wavelengths must be positive");
+            }
+        m->lambda_um.assign(lambda_um, lambda_um + n_lambda);
+    }
     *out = m;
     return MCRT_OK;
 }
@@ -406,6 +441,9 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
     }
     s->image_elems = off;
     const mcrt_grid *g = medium->grid;
+    feature_constants(g->box, medium->density.data(), g->n_cells,
+                      medium->lambda_um.empty() ? nullptr : medium->lambda_um.data(), medium->n_lambda, s->r_out,
+                      s->rho_mean, s->lamf);
     std::vector<float> stored;
     const float *dens = medium->density.data();
     s->n_store = g->n_cells;
@@ -532,7 +570,7 @@ int mcrt_result_create(mcrt_sim *sim, mcrt_result **out)
 
 template <typename Real, typename ImgT, int G>
 static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
-                    mcrt_result *r)
+                    mcrt_result *r, mcrt_histories *hist = nullptr)
 {
     const mcrt_medium *m = s->medium;
     const mcrt_grid *g = m->grid;
@@ -543,6 +581,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         optics[l].albedo = (Real)m->albedo[l];
         optics[l].g = (Real)m->g[l];
         optics[l].L0 = (Real)(s->source->L[l] / (double)n_per_lambda);
+        optics[l].lamf = (Real)s->lamf[l];
     }
     HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_zero(r->d_counter, sizeof(unsigned long long), st));
@@ -581,6 +620,20 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     v.key0 = (uint32_t)(seed & 0xffffffffu);
     v.key1 = (uint32_t)(seed >> 32);
     v.model = 0;
+    v.r_out = (Real)s->r_out;
+    v.rho_mean = (Real)s->rho_mean;
+    if (s->prop) {
+        v.learned = 1;
+        v.alpha = (Real)s->alpha;
+        v.mlp64 = s->prop->d_theta64;
+        a.mlp_frags = s->prop->d_frags;
+        a.mlp_bias = s->prop->d_bias;
+    }
+    if (hist) {
+        v.hist = (Real *)hist->d_hist;
+        v.hist_total = (Real *)hist->d_total;
+        v.hist_events = hist->events;
+    }
     a.optics = (const Optics<Real> *)s->d_optics;
     a.ins = (const InsDesc<Real> *)s->d_ins;
     a.count = count;
@@ -769,6 +822,7 @@ int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_
             return fail(MCRT_EINVAL, "batch_run_into: sims must share context and precision");
         if (sims[i]->medium->grid->type != kCartesian)
             return fail(MCRT_EINVAL, "batch_run_into: batched runs take Cartesian grids");
+        if (sims[i]->prop) return fail(MCRT_EINVAL, "batch_run_into: batched runs use plain direction sampling");
         if (n_per_lambda[i] == 0 || n_per_lambda[i] > (uint64_t(1) << 32))
             return fail(MCRT_EINVAL, "batch_run_into: n_per_lambda must be in 1 .. 2^32");
     }
@@ -1022,3 +1076,533 @@ int mcrt_result_stats(const mcrt_result *res, mcrt_stats *stats)
     return MCRT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned direction proposal
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void proposal_free(mcrt_proposal *p)
+{
+    dev_free(p->d_theta);
+    dev_free(p->d_m);
+    dev_free(p->d_v);
+    dev_free(p->d_frags);
+    dev_free(p->d_bias);
+    dev_free(p->d_theta64);
+}
+
+void histories_free(mcrt_histories *h)
+{
+    dev_free(h->d_hist);
+    dev_free(h->d_total);
+    dev_free(h->d_X);
+    dev_free(h->d_KP);
+    dev_free(h->d_C);
+}
+
+// Seeded uniform fan-in initialisation: weights U(-b, b), b = scale sqrt(6 / fan_in),
+// from a 64-bit linear congruential stream; biases zero.
+void init_params(uint64_t seed, float scale, std::vector<float> &theta)
+{
+    theta.assign((size_t)kMlpParams, 0.0f);
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    auto uni = [&x]() {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        return (double)(x >> 11) * 0x1p-53;
+    };
+    struct Blk {
+        int off, n, fan;
+    } blk[3] = {{0, 9 * 64, 9}, {640, 64 * 64, 64}, {4800, 64 * 40, 64}};
+    for (auto &b : blk) {
+        double bound = scale * std::sqrt(6.0 / b.fan);
+        for (int i = 0; i < b.n; ++i) theta[(size_t)(b.off + i)] = (float)((2.0 * uni() - 1.0) * bound);
+    }
+}
+
+int proposal_repack(mcrt_proposal *p)
+{
+    hipStream_t st = p->ctx->stream;
+    HIP_TRY(launch_proposal_pack(p->d_theta, p->d_frags, p->d_bias, p->d_theta64, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MCRT_OK;
+}
+
+// Device scratch of one gradient pass.
+struct GradScratch {
+    float *partial = nullptr;
+    double *loss_partial = nullptr;
+    ~GradScratch()
+    {
+        dev_free(partial);
+        dev_free(loss_partial);
+    }
+};
+
+int grad_waves(const mcrt_context *ctx, int64_t m)
+{
+    int64_t w = (m + 63) / 64;
+    int64_t cap = 2 * (int64_t)ctx->n_cu;
+    if (w > cap) w = cap;
+    return (int)std::max<int64_t>(w, 1);
+}
+
+} // namespace
+
+int mcrt_proposal_create(mcrt_context *ctx, const mcrt_mlp_desc *desc, mcrt_proposal **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "proposal_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !desc) return fail(MCRT_EINVAL, "proposal_create: NULL argument");
+    if (desc->n_in != 9 || desc->n_hidden != 64 || desc->n_out != 40)
+        return fail(MCRT_EINVAL, "proposal_create: only the 9 -> 64 -> 64 -> 40 network is supported");
+    if (!(desc->init_scale >= 0.0f) || !std::isfinite(desc->init_scale))
+        return fail(MCRT_EINVAL, "proposal_create: init_scale must be finite and >= 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto *p = new mcrt_proposal;
+    p->ctx = ctx;
+    int rc = dev_alloc((void **)&p->d_theta, kMlpParams * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&p->d_m, kMlpParams * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&p->d_v, kMlpParams * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&p->d_frags, kFragAllElems * sizeof(uint16_t));
+    if (!rc) rc = dev_alloc((void **)&p->d_bias, 176 * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&p->d_theta64, kMlpParams * sizeof(double));
+    if (rc) {
+        proposal_free(p);
+        delete p;
+        return rc;
+    }
+    std::vector<float> theta;
+    init_params(desc->init_seed, desc->init_scale, theta);
+    rc = mcrt_proposal_set_params(p, theta.data(), theta.size());
+    if (rc) {
+        std::string msg = g_err;
+        proposal_free(p);
+        delete p;
+        g_err = msg;
+        return rc;
+    }
+    *out = p;
+    return MCRT_OK;
+}
+
+void mcrt_proposal_destroy(mcrt_proposal *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    proposal_free(p);
+    delete p;
+}
+
+int mcrt_proposal_set_params(mcrt_proposal *p, const float *theta, size_t count)
+{
+    if (!p || !theta) return fail(MCRT_EINVAL, "proposal_set_params: NULL argument");
+    if (count != (size_t)kMlpParams) return fail(MCRT_EINVAL, "proposal_set_params: count must be 7400");
+    BusyGuard guard(p->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "proposal_set_params: the proposal is in use");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t st = p->ctx->stream;
+    HIP_TRY(hipMemcpyAsync(p->d_theta, theta, kMlpParams * sizeof(float), hipMemcpyDefault, st));
+    HIP_TRY(launch_fill_zero(p->d_m, kMlpParams * sizeof(float), st));
+    HIP_TRY(launch_fill_zero(p->d_v, kMlpParams * sizeof(float), st));
+    p->step = 0;
+    return proposal_repack(p);
+}
+
+int mcrt_proposal_get_params(const mcrt_proposal *p, float *theta, size_t count)
+{
+    if (!p || !theta) return fail(MCRT_EINVAL, "proposal_get_params: NULL argument");
+    if (count < (size_t)kMlpParams) return fail(MCRT_EINVAL, "proposal_get_params: count must be >= 7400");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipMemcpyAsync(theta, p->d_theta, kMlpParams * sizeof(float), hipMemcpyDefault, p->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    return MCRT_OK;
+}
+
+int mcrt_proposal_get_weights(const mcrt_proposal *p, uint16_t *bf16, size_t count)
+{
+    if (!p || !bf16) return fail(MCRT_EINVAL, "proposal_get_weights: NULL argument");
+    if (count < (size_t)kMlpParams) return fail(MCRT_EINVAL, "proposal_get_weights: count must be >= 7400");
+    std::vector<float> theta((size_t)kMlpParams);
+    int rc = mcrt_proposal_get_params(p, theta.data(), theta.size());
+    if (rc) return rc;
+    std::vector<uint16_t> w((size_t)kMlpParams);
+    for (int i = 0; i < kMlpParams; ++i) {
+        float r = Bf16<float>::round(theta[(size_t)i]);
+        uint32_t b;
+        std::memcpy(&b, &r, sizeof b);
+        w[(size_t)i] = (uint16_t)(b >> 16);
+    }
+    HIP_TRY(hipMemcpy(bf16, w.data(), w.size() * sizeof(uint16_t), hipMemcpyDefault));
+    return MCRT_OK;
+}
+
+int mcrt_proposal_forward(mcrt_proposal *p, const float *X, int64_t n, float *out)
+{
+    if (!p || (n > 0 && (!X || !out))) return fail(MCRT_EINVAL, "proposal_forward: NULL argument");
+    if (n < 0 || n > (int64_t(1) << 34)) return fail(MCRT_EINVAL, "proposal_forward: n out of range");
+    if (n == 0) return MCRT_OK;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t st = p->ctx->stream;
+    float *dX = nullptr, *dO = nullptr;
+    int rc = dev_alloc((void **)&dX, (size_t)n * 9 * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&dO, (size_t)n * 40 * sizeof(float));
+    hipError_t e = hipSuccess;
+    if (!rc) {
+        e = hipMemcpyAsync(dX, X, (size_t)n * 9 * sizeof(float), hipMemcpyDefault, st);
+        if (e == hipSuccess) e = launch_proposal_forward(p->d_frags, p->d_bias, dX, n, dO, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, dO, (size_t)n * 40 * sizeof(float), hipMemcpyDefault, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    dev_free(dX);
+    dev_free(dO);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, std::string("proposal_forward: ") + hipGetErrorString(e));
+    return MCRT_OK;
+}
+
+// One pass of the gradient kernel over device samples, summed by the Adam
+// kernel (update = 0) or followed by an Adam step (update = 1).
+static int grad_pass(mcrt_proposal *p, const float *dX, const float *dKP, const float *dC, int64_t n, int64_t m,
+                     int random, uint64_t seed, float scale, const AdamArgs &adam_in, GradScratch &scr)
+{
+    hipStream_t st = p->ctx->stream;
+    const int waves = grad_waves(p->ctx, m);
+    if (!scr.partial) {
+        int rc = dev_alloc((void **)&scr.partial, (size_t)waves * kGradStrideFloats * sizeof(float));
+        if (!rc) rc = dev_alloc((void **)&scr.loss_partial, (size_t)waves * sizeof(double));
+        if (rc) return rc;
+    }
+    GradArgs g{};
+    g.frags = p->d_frags;
+    g.bias = p->d_bias;
+    g.X = dX;
+    g.KP = dKP;
+    g.C = dC;
+    g.n = n;
+    g.m = m;
+    g.random = random;
+    g.key0 = (uint32_t)(seed & 0xffffffffu);
+    g.key1 = (uint32_t)(seed >> 32);
+    g.step = (uint32_t)adam_in.step;
+    g.scale = scale;
+    g.partial = scr.partial;
+    g.loss_partial = scr.loss_partial;
+    HIP_TRY(launch_proposal_grad(g, waves, st));
+    HIP_TRY(launch_proposal_adam(scr.partial, waves, scr.loss_partial, adam_in, st));
+    return MCRT_OK;
+}
+
+int mcrt_proposal_grad(mcrt_proposal *p, const float *X, const float *KP, const float *C, int64_t n, double *loss,
+                       float *grad)
+{
+    if (!p || !X || !KP || !C || !grad) return fail(MCRT_EINVAL, "proposal_grad: NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31)) return fail(MCRT_EINVAL, "proposal_grad: n must be in 1 .. 2^31");
+    BusyGuard guard(p->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "proposal_grad: the proposal is in use");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t st = p->ctx->stream;
+    std::vector<float> hc((size_t)n);
+    HIP_TRY(hipMemcpy(hc.data(), C, (size_t)n * sizeof(float), hipMemcpyDefault));
+    double csum = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(hc[(size_t)i] >= 0.0f) || !std::isfinite(hc[(size_t)i]))
+            return fail(MCRT_EINVAL, "proposal_grad: weights must be finite and >= 0");
+        csum += hc[(size_t)i];
+    }
+    if (!(csum > 0.0)) return fail(MCRT_EINVAL, "proposal_grad: the weights sum to zero");
+    float *dX = nullptr, *dKP = nullptr, *dC = nullptr, *dG = nullptr;
+    double *dL = nullptr;
+    int rc = dev_alloc((void **)&dX, (size_t)n * 9 * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&dKP, (size_t)n * 3 * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&dC, (size_t)n * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&dG, kMlpParams * sizeof(float));
+    if (!rc) rc = dev_alloc((void **)&dL, sizeof(double));
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(dX, X, (size_t)n * 9 * sizeof(float), hipMemcpyDefault, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dKP, KP, (size_t)n * 3 * sizeof(float), hipMemcpyDefault, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dC, hc.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_grad: ") + hipGetErrorString(e));
+    }
+    if (!rc) {
+        GradScratch scr;
+        AdamArgs a{};
+        a.step = 1;
+        a.update = 0;
+        a.grad_out = dG;
+        a.loss_out = dL;
+        rc = grad_pass(p, dX, dKP, dC, n, n, 0, 0, (float)(1.0 / csum), a, scr);
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(grad, dG, kMlpParams * sizeof(float), hipMemcpyDefault, st);
+            double l = 0.0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&l, dL, sizeof(double), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_grad: ") + hipGetErrorString(e));
+            if (loss) *loss = l;
+        }
+    }
+    dev_free(dX);
+    dev_free(dKP);
+    dev_free(dC);
+    dev_free(dG);
+    dev_free(dL);
+    return rc;
+}
+
+void mcrt_train_opts_default(mcrt_train_opts *o)
+{
+    if (!o) return;
+    o->epochs = 4;
+    o->batch = 8192;
+    o->lr = 2e-3f;
+    o->beta1 = 0.9f;
+    o->beta2 = 0.999f;
+    o->eps = 1e-8f;
+    o->seed = 1;
+}
+
+int mcrt_proposal_train(mcrt_proposal *p, const mcrt_histories *h, const mcrt_train_opts *opt, double *final_loss)
+{
+    if (!p || !h) return fail(MCRT_EINVAL, "proposal_train: NULL argument");
+    if (h->ctx != p->ctx) return fail(MCRT_EINVAL, "proposal_train: proposal and histories of different contexts");
+    mcrt_train_opts o;
+    mcrt_train_opts_default(&o);
+    if (opt) o = *opt;
+    if (o.epochs < 0 || o.batch < 64 || o.batch > (1 << 24) || !(o.lr > 0.0f) || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) ||
+        !(o.beta2 >= 0.0f && o.beta2 < 1.0f) || !(o.eps > 0.0f))
+        return fail(MCRT_EINVAL, "proposal_train: epochs >= 0, batch in 64 .. 2^24, lr > 0, betas in [0, 1), eps > 0");
+    if (h->n_samples <= 0 || !(h->c_sum > 0.0)) return fail(MCRT_EINVAL, "proposal_train: no training samples");
+    BusyGuard guard(p->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "proposal_train: the proposal is in use");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t st = p->ctx->stream;
+    const int64_t steps = (int64_t)o.epochs * ((h->n_samples + o.batch - 1) / o.batch);
+    const float scale = (float)((double)h->n_samples / (h->c_sum * (double)o.batch));
+    GradScratch scr;
+    double *dL = nullptr;
+    int rc = dev_alloc((void **)&dL, sizeof(double));
+    if (rc) return rc;
+    for (int64_t k = 0; k < steps && !rc; ++k) {
+        AdamArgs a{};
+        a.theta = p->d_theta;
+        a.m = p->d_m;
+        a.v = p->d_v;
+        a.lr = o.lr;
+        a.b1 = o.beta1;
+        a.b2 = o.beta2;
+        a.eps = o.eps;
+        a.step = ++p->step;
+        a.update = 1;
+        a.loss_out = dL;
+        rc = grad_pass(p, h->d_X, h->d_KP, h->d_C, h->n_samples, o.batch, 1, o.seed, scale, a, scr);
+        if (!rc) {
+            hipError_t e = launch_proposal_pack(p->d_theta, p->d_frags, p->d_bias, p->d_theta64, st);
+            if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_train: ") + hipGetErrorString(e));
+        }
+    }
+    double l = 0.0;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&l, dL, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_train: ") + hipGetErrorString(e));
+    }
+    dev_free(dL);
+    if (!rc && final_loss) *final_loss = steps > 0 ? l : 0.0;
+    return rc;
+}
+
+int mcrt_proposal_eval(mcrt_proposal *p, const mcrt_histories *h, double *loss)
+{
+    if (!p || !h || !loss) return fail(MCRT_EINVAL, "proposal_eval: NULL argument");
+    if (h->ctx != p->ctx) return fail(MCRT_EINVAL, "proposal_eval: proposal and histories of different contexts");
+    if (h->n_samples <= 0 || !(h->c_sum > 0.0)) return fail(MCRT_EINVAL, "proposal_eval: no samples");
+    BusyGuard guard(p->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "proposal_eval: the proposal is in use");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    GradScratch scr;
+    double *dL = nullptr;
+    int rc = dev_alloc((void **)&dL, sizeof(double));
+    if (rc) return rc;
+    AdamArgs a{};
+    a.step = 1;
+    a.update = 0;
+    a.loss_out = dL;
+    rc = grad_pass(p, h->d_X, h->d_KP, h->d_C, h->n_samples, h->n_samples, 0, 0, (float)(1.0 / h->c_sum), a, scr);
+    double l = 0.0;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&l, dL, sizeof(double), hipMemcpyDeviceToHost, p->ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->ctx->stream);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_eval: ") + hipGetErrorString(e));
+    }
+    dev_free(dL);
+    if (!rc) *loss = l;
+    return rc;
+}
+
+int mcrt_sim_set_proposal(mcrt_sim *sim, mcrt_proposal *p, double alpha)
+{
+    if (!sim) return fail(MCRT_EINVAL, "sim_set_proposal: NULL sim");
+    BusyGuard guard(sim->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "sim_set_proposal: the simulation is running");
+    if (!p) {
+        sim->prop = nullptr;
+        return MCRT_OK;
+    }
+    if (p->ctx != sim->ctx) return fail(MCRT_EINVAL, "sim_set_proposal: proposal of another context");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(MCRT_EINVAL, "sim_set_proposal: alpha must lie in (0, 1]");
+    if (sim->medium->lambda_um.empty())
+        return fail(MCRT_EINVAL, "sim_set_proposal: the medium needs wavelengths (lambda_um) for the features");
+    sim->prop = p;
+    sim->alpha = alpha;
+    return MCRT_OK;
+}
+
+int mcrt_proposal_collect(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                          int32_t max_events, mcrt_result *res, mcrt_histories **out)
+{
+    if (!out) return fail(MCRT_EINVAL, "proposal_collect: out is NULL");
+    *out = nullptr;
+    if (!sim || !res) return fail(MCRT_EINVAL, "proposal_collect: NULL sim or result");
+    if (res->sim != sim) return fail(MCRT_EINVAL, "proposal_collect: result belongs to another sim");
+    if (sim->prop) return fail(MCRT_EINVAL, "proposal_collect: histories come from plain runs (detach the proposal)");
+    if (sim->medium->lambda_um.empty())
+        return fail(MCRT_EINVAL, "proposal_collect: the medium needs wavelengths (lambda_um) for the features");
+    if (max_events < 1 || max_events > 4096) return fail(MCRT_EINVAL, "proposal_collect: max_events in 1 .. 4096");
+    if (n_per_lambda == 0 || n_per_lambda > (uint64_t(1) << 32) || first_id > n_per_lambda ||
+        count > n_per_lambda - first_id || count == 0)
+        return fail(MCRT_EINVAL, "proposal_collect: bad packet range");
+    const uint64_t npk = count * (uint64_t)sim->medium->n_lambda;
+    if (npk > (uint64_t(1) << 32)) return fail(MCRT_EINVAL, "proposal_collect: at most 2^32 packets per collection");
+    BusyGuard guard(sim->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "proposal_collect: the simulation is already running");
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    hipStream_t st = sim->ctx->stream;
+    auto *h = new mcrt_histories;
+    h->ctx = sim->ctx;
+    h->fp64 = sim->opt.precision == MCRT_FP64_VALIDATE;
+    h->n_packets = (int64_t)npk;
+    h->events = max_events;
+    const size_t rb = h->fp64 ? sizeof(double) : sizeof(float);
+    const size_t hist_bytes = (size_t)npk * (size_t)max_events * kHistFloats * rb;
+    int rc = dev_alloc(&h->d_hist, hist_bytes);
+    if (!rc) rc = dev_alloc(&h->d_total, (size_t)npk * rb);
+    if (!rc) {
+        hipError_t e = launch_fill_zero(h->d_hist, hist_bytes, st);
+        if (e == hipSuccess) e = launch_fill_zero(h->d_total, (size_t)npk * rb, st);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_collect: ") + hipGetErrorString(e));
+    }
+    int run_rc = MCRT_OK;
+    if (!rc) {
+        const bool oct = sim->medium->grid->type == kOctree;
+        if (!h->fp64) {
+            run_rc = oct ? run_impl<float, float, kOctree>(sim, n_per_lambda, first_id, count, seed, res, h)
+                         : run_impl<float, float, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, h);
+        } else {
+            run_rc = oct ? run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res, h)
+                         : run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, h);
+        }
+        if (run_rc != MCRT_OK && run_rc != MCRT_ELIMIT) rc = run_rc;
+    }
+    // compaction into training samples
+    uint32_t *d_count = nullptr;
+    uint64_t *d_off = nullptr, *d_bs = nullptr, *d_tot = nullptr;
+    double *d_csum = nullptr;
+    if (!rc) {
+        const int64_t nb = ((int64_t)npk + 1023) / 1024;
+        rc = dev_alloc((void **)&d_count, (size_t)npk * sizeof(uint32_t));
+        if (!rc) rc = dev_alloc((void **)&d_off, (size_t)npk * sizeof(uint64_t));
+        if (!rc) rc = dev_alloc((void **)&d_bs, (size_t)nb * sizeof(uint64_t));
+        if (!rc) rc = dev_alloc((void **)&d_tot, sizeof(uint64_t));
+        if (!rc) rc = dev_alloc((void **)&d_csum, sizeof(double));
+    }
+    if (!rc) {
+        uint64_t ns = 0;
+        hipError_t e = launch_hist_count(h->d_hist, h->d_total, h->fp64, (int64_t)npk, max_events, d_count, d_off,
+                                         d_bs, d_tot, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&ns, d_tot, sizeof(ns), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_collect: ") + hipGetErrorString(e));
+        h->n_samples = (int64_t)ns;
+        if (!rc && ns > 0) {
+            rc = dev_alloc((void **)&h->d_X, (size_t)ns * 9 * sizeof(float));
+            if (!rc) rc = dev_alloc((void **)&h->d_KP, (size_t)ns * 3 * sizeof(float));
+            if (!rc) rc = dev_alloc((void **)&h->d_C, (size_t)ns * sizeof(float));
+            if (!rc) {
+                e = launch_hist_write(h->d_hist, h->d_total, h->fp64, (int64_t)npk, max_events, d_off, h->d_X,
+                                      h->d_KP, h->d_C, st);
+                if (e == hipSuccess) e = launch_sum_f32(h->d_C, (int64_t)ns, d_csum, st);
+                if (e == hipSuccess) e = hipMemcpyAsync(&h->c_sum, d_csum, sizeof(double), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("proposal_collect: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    dev_free(d_count);
+    dev_free(d_off);
+    dev_free(d_bs);
+    dev_free(d_tot);
+    dev_free(d_csum);
+    if (rc) {
+        std::string msg = g_err;
+        histories_free(h);
+        delete h;
+        g_err = msg;
+        return rc;
+    }
+    *out = h;
+    return run_rc;
+}
+
+int mcrt_histories_info(const mcrt_histories *h, int64_t *n_packets, int32_t *max_events, int64_t *n_samples,
+                        double *weight_sum)
+{
+    if (!h) return fail(MCRT_EINVAL, "histories_info: NULL histories");
+    if (n_packets) *n_packets = h->n_packets;
+    if (max_events) *max_events = h->events;
+    if (n_samples) *n_samples = h->n_samples;
+    if (weight_sum) *weight_sum = h->c_sum;
+    return MCRT_OK;
+}
+
+int mcrt_histories_records(const mcrt_histories *h, double *records, size_t count, double *totals,
+                           size_t count_totals)
+{
+    if (!h || !records || !totals) return fail(MCRT_EINVAL, "histories_records: NULL argument");
+    const size_t nrec = (size_t)h->n_packets * (size_t)h->events * kHistFloats;
+    if (count < nrec || count_totals < (size_t)h->n_packets)
+        return fail(MCRT_EINVAL, "histories_records: output buffer too small");
+    HIP_TRY(hipSetDevice(h->ctx->device));
+    if (h->fp64) {
+        HIP_TRY(hipMemcpy(records, h->d_hist, nrec * sizeof(double), hipMemcpyDefault));
+        HIP_TRY(hipMemcpy(totals, h->d_total, (size_t)h->n_packets * sizeof(double), hipMemcpyDefault));
+        return MCRT_OK;
+    }
+    std::vector<float> a(nrec), b((size_t)h->n_packets);
+    HIP_TRY(hipMemcpy(a.data(), h->d_hist, nrec * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(b.data(), h->d_total, b.size() * sizeof(float), hipMemcpyDeviceToHost));
+    std::vector<double> da(a.begin(), a.end()), db(b.begin(), b.end());
+    HIP_TRY(hipMemcpy(records, da.data(), nrec * sizeof(double), hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(totals, db.data(), db.size() * sizeof(double), hipMemcpyDefault));
+    return MCRT_OK;
+}
+
+int mcrt_histories_samples(const mcrt_histories *h, float *X, float *KP, float *C, size_t n)
+{
+    if (!h || !X || !KP || !C) return fail(MCRT_EINVAL, "histories_samples: NULL argument");
+    if (n < (size_t)h->n_samples) return fail(MCRT_EINVAL, "histories_samples: output buffers too small");
+    if (h->n_samples == 0) return MCRT_OK;
+    HIP_TRY(hipSetDevice(h->ctx->device));
+    HIP_TRY(hipMemcpy(X, h->d_X, (size_t)h->n_samples * 9 * sizeof(float), hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(KP, h->d_KP, (size_t)h->n_samples * 3 * sizeof(float), hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(C, h->d_C, (size_t)h->n_samples * sizeof(float), hipMemcpyDefault));
+    return MCRT_OK;
+}
+
+void mcrt_histories_destroy(mcrt_histories *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->ctx->device);
+    histories_free(h);
+    delete h;
+}

@@ -663,13 +663,25 @@ template <> struct Bf16<double> {
     MCRT_HD static double round(double x) { return (double)Bf16<float>::round((float)x); }
 };
 
+// Which optional features a kernel variant carries is a compile-time
+// property of its sink (Sink::kLearn, Sink::kHist); the View's runtime fields
+// then select them.  Variants without a feature compile without its code.
+template <typename Sink, typename Real, typename ImgT, int G> MCRT_HD bool learned_on(const View<Real, ImgT, G> &v)
+{
+    return Sink::kLearn && v.learned != 0;
+}
+template <typename Sink, typename Real, typename ImgT, int G> MCRT_HD bool hist_on(const View<Real, ImgT, G> &v)
+{
+    return Sink::kHist && v.hist != nullptr;
+}
+
 // Packet end: the total image flux of the packet goes to the histories.
-template <typename Real, typename ImgT, int G>
+template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void end_packet(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
     ln.mode = kDead;
     ln.marching = false;
-    if (v.hist) v.hist_total[ln.slot] = ln.flux;
+    if (hist_on<Sink>(v)) v.hist_total[ln.slot] = ln.flux;
 }
 
 // Features: position / r_out, incoming direction (zero at emission), the
@@ -731,39 +743,41 @@ template <typename Real> struct Consts4 {
 };
 
 // Direction from the proposal q = alpha p_phys + (1 - alpha) sum_j pi_j vMF_j
-// given the network outputs; the packet carries W = p_phys / q.  Then the
-// next propagation (after a scattering: the event count and cap first).
-template <typename Real, typename ImgT, int G>
-MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, const Real o[40])
+// given the network outputs o[40]; the packet carries W = p_phys / q.  Then the
+// next propagation (after a scattering: the event count and cap first).  The
+// outputs are turned into the mixture in place (o[j] = pi_j, o[8+3j..] = mu_j,
+// o[32+j] = kappa_j), so o may be a row of a shared-memory tile.
+template <typename Sink, typename Real, typename ImgT, int G, typename Ptr>
+MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Ptr o)
 {
-    Real pi[8], mu[8][3], kap[8];
     Real mx = o[0];
     for (int j = 1; j < 8; ++j)
         if (o[j] > mx) mx = o[j];
     Real sum = Real(0);
     for (int j = 0; j < 8; ++j) {
-        pi[j] = Math<Real>::e_exp(o[j] - mx);
-        sum = sum + pi[j];
+        Real e = Math<Real>::e_exp(o[j] - mx);
+        o[j] = e;
+        sum = sum + e;
     }
     for (int j = 0; j < 8; ++j) {
-        pi[j] = pi[j] / sum;
+        o[j] = o[j] / sum;
         Real a = o[8 + 3 * j], b = o[9 + 3 * j], c = o[10 + 3 * j];
         Real nrm = sqrt(a * a + b * b + c * c);
         if (nrm > Real(0)) {
-            mu[j][0] = a / nrm;
-            mu[j][1] = b / nrm;
-            mu[j][2] = c / nrm;
+            o[8 + 3 * j] = a / nrm;
+            o[9 + 3 * j] = b / nrm;
+            o[10 + 3 * j] = c / nrm;
         } else {
-            mu[j][0] = Real(0);
-            mu[j][1] = Real(0);
-            mu[j][2] = Real(1);
+            o[8 + 3 * j] = Real(0);
+            o[9 + 3 * j] = Real(0);
+            o[10 + 3 * j] = Real(1);
         }
         Real sj = o[32 + j];
         Real sp = Math<Real>::e_log1p(Math<Real>::e_exp(-fabs(sj))) + (sj > Real(0) ? sj : Real(0));
         Real k = sp + Real(1e-3);
         if (k < Real(1e-3)) k = Real(1e-3);
         if (k > Real(1e3)) k = Real(1e3);
-        kap[j] = k;
+        o[32 + j] = k;
     }
     Stream st = stream_of(v, ln);
     const bool emis = ln.emis_dir;
@@ -793,19 +807,19 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
         Real w = (u3 - v.alpha) / (Real(1) - v.alpha), c = Real(0);
         int j = 7;
         for (int i = 0; i < 8; ++i) {
-            c = c + pi[i];
+            c = c + o[i];
             if (w < c) {
                 j = i;
                 break;
             }
         }
-        Real kj = kap[j];
+        Real kj = o[32 + j];
         Real cw = Real(1) + Math<Real>::e_log(u1 + (Real(1) - u1) * Math<Real>::e_exp(Real(-2) * kj)) / kj;
         if (cw < Real(-1)) cw = Real(-1);
         if (cw > Real(1)) cw = Real(1);
-        kp[0] = mu[j][0];
-        kp[1] = mu[j][1];
-        kp[2] = mu[j][2];
+        kp[0] = o[8 + 3 * j];
+        kp[1] = o[9 + 3 * j];
+        kp[2] = o[10 + 3 * j];
         rotate(kp, cw, Consts<Real>::two_pi() * u2);
     }
     Real pphys;
@@ -818,11 +832,11 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
     }
     Real qv = Real(0);
     for (int j = 0; j < 8; ++j) {
-        Real kj = kap[j];
-        Real dot = mu[j][0] * kp[0] + mu[j][1] * kp[1] + mu[j][2] * kp[2];
+        Real kj = o[32 + j];
+        Real dot = o[8 + 3 * j] * kp[0] + o[9 + 3 * j] * kp[1] + o[10 + 3 * j] * kp[2];
         Real fj = kj / (Consts<Real>::two_pi() * -Math<Real>::e_expm1(Real(-2) * kj)) *
                   Math<Real>::e_exp(kj * (dot - Real(1)));
-        qv = qv + pi[j] * fj;
+        qv = qv + o[j] * fj;
     }
     Real q = v.alpha * pphys + (Real(1) - v.alpha) * qv;
     ln.L = (emis ? ln.L0 : ln.L) * (pphys / q);
@@ -834,7 +848,7 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
         if (ln.e > v.event_cap) {
             ty.truncated += (double)ln.L;
             ty.capped++;
-            end_packet(v, ln);
+            end_packet<Sink>(v, ln);
             return;
         }
     }
@@ -843,29 +857,29 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
 
 // Scattering: new HG direction (or the learned proposal), then the next
 // propagation (or the event cap).
-template <typename Real, typename ImgT, int G>
+template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 {
-    if (v.learned) {
+    if (learned_on<Sink>(v)) {
         ln.mode = kNeedDir;
         ln.emis_dir = false;
         ln.marching = false;
         return;
     }
     Real f[9];
-    if (v.hist) event_features(v, ln, true, f);
+    if (hist_on<Sink>(v)) event_features(v, ln, true, f);
     Stream st = stream_of(v, ln);
     Real u1 = st.template slot<Real>((uint32_t)(8 * ln.e + 1));
     Real u2 = st.template slot<Real>((uint32_t)(8 * ln.e + 2));
     Real mu = hg_sample(ln.opt.g, u1);
     Real phi = Consts<Real>::two_pi() * u2;
     rotate(ln.k, mu, phi);
-    if (v.hist) record_event(v, ln, ln.e, f, ln.k, ln.L);
+    if (hist_on<Sink>(v)) record_event(v, ln, ln.e, f, ln.k, ln.L);
     ln.e = ln.e + 1;
     if (ln.e > v.event_cap) {
         ty.truncated += (double)ln.L;
         ty.capped++;
-        end_packet(v, ln);
+        end_packet<Sink>(v, ln);
         return;
     }
     begin_prop(v, ln);
@@ -873,16 +887,16 @@ MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 
 // After the emission peel-offs: the emission direction (already sampled, or
 // left to the learned proposal for point sources), then the first propagation.
-template <typename Real, typename ImgT, int G>
+template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void emission_done(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
-    if (v.learned && v.src_type != kExpDisk) {
+    if (learned_on<Sink>(v) && v.src_type != kExpDisk) {
         ln.mode = kNeedDir;
         ln.emis_dir = true;
         ln.marching = false;
         return;
     }
-    if (v.hist) {
+    if (hist_on<Sink>(v)) {
         Real f[9];
         event_features(v, ln, false, f);
         record_event(v, ln, 0, f, ln.k, ln.L0);
@@ -891,7 +905,7 @@ MCRT_HD void emission_done(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 }
 
 // Launches packet (lam, id): position, direction, emission peel-offs.
-template <typename Real, typename ImgT, int G>
+template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uint32_t lam, uint32_t id,
                     uint32_t slot)
 {
@@ -919,7 +933,7 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
         ln.r[1] = v.src_pos[1];
         ln.r[2] = v.src_pos[2];
     }
-    if (!(v.learned && v.src_type != kExpDisk)) {
+    if (!(learned_on<Sink>(v) && v.src_type != kExpDisk)) {
         Real u4, u5, u6, u7;
         st.template pair<Real>(2, u4, u5);
         st.template pair<Real>(3, u6, u7);
@@ -950,7 +964,7 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
 {
     if (ln.mode == kLaunched) {
         if (v.n_ins > 0) begin_peel(v, ln, 0, true);
-        else emission_done(v, ln);
+        else emission_done<Sink>(v, ln);
         return;
     }
     if (ln.mode == kPeelEmit || ln.mode == kPeelScat) {
@@ -966,7 +980,7 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
                 long long idx = in.offset + ((long long)ln.lam * in.ny + (long long)py) * in.nx + (long long)px;
                 Real val = ln.wpeel * Math<Real>::e_exp(-ln.tau);
                 sink.pixel(v.images + idx, (ImgT)val);
-                if (v.hist) ln.flux = ln.flux + val * in.inv4pid2;
+                if (hist_on<Sink>(v)) ln.flux = ln.flux + val * in.inv4pid2;
                 ty.peel_adds++;
             }
         }
@@ -975,9 +989,9 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         if (j < v.n_ins) {
             begin_peel(v, ln, j, emission);
         } else if (emission) {
-            emission_done(v, ln);
+            emission_done<Sink>(v, ln);
         } else {
-            scatter(v, ln, ty);
+            scatter<Sink>(v, ln, ty);
         }
         return;
     }
@@ -985,13 +999,13 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         const Real Epath = ln.E;
         ty.escaped += (double)(ln.L * Epath);
         if (ln.nseg == 0 || ln.opt.albedo == Real(0) || ln.tau == Real(0)) {
-            end_packet(v, ln);
+            end_packet<Sink>(v, ln);
             return;
         }
         Real Ls = ln.opt.albedo * ln.L * (Real(1) - Epath);
         if (Ls < v.w_min * ln.L0) {
             ty.truncated += (double)Ls;
-            end_packet(v, ln);
+            end_packet<Sink>(v, ln);
             return;
         }
         Stream st = stream_of(v, ln);
@@ -1011,28 +1025,32 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
         ln.r[2] = ln.r[2] + ln.k[2] * dist;
         ty.events++;
         if (v.n_ins > 0) begin_peel(v, ln, 0, false);
-        else scatter(v, ln, ty);
+        else scatter<Sink>(v, ln, ty);
         return;
     }
-    end_packet(v, ln);
+    end_packet<Sink>(v, ln);
 }
 
 template <typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void settle(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
-    while (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) finish_march(v, ln, ty, sink);
+    if constexpr (Sink::kLearn) {
+        while (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) finish_march(v, ln, ty, sink);
+    } else {
+        while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
+    }
 }
 
 // One sample at a time: features, network, proposal (host simulator and the
 // FP64 validation kernel; the FP32 kernel evaluates the network per wave).
-template <typename Real, typename ImgT, int G, typename Sink>
-MCRT_HD void resolve_direction_scalar(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
+// Leaves the lane marching, dead, or with a finished march to settle.
+template <typename Sink, typename Real, typename ImgT, int G>
+MCRT_HD void resolve_direction_scalar(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 {
     Real f[9], o[40];
     event_features(v, ln, !ln.emis_dir, f);
     mlp_forward_scalar(v.mlp64, f, o);
-    apply_proposal(v, ln, ty, o);
-    settle(v, ln, ty, sink);
+    apply_proposal<Sink>(v, ln, ty, (Real *)o);
 }
 
 } // namespace mcrt

@@ -24,10 +24,12 @@
 #define MCRT_HD __device__ __forceinline__
 #include "transport_core.h"
 #include "internal.h"
+#include "proposal.h"
 
 namespace mcrt {
 
-struct DevSink {
+template <bool LEARN, bool HIST> struct DevSink {
+    static constexpr bool kLearn = LEARN, kHist = HIST;
     __device__ __forceinline__ void deposit(double *p, double v)
     {
         if (v != 0.0) unsafeAtomicAdd(p, v);
@@ -53,7 +55,49 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
-template <typename Real, typename ImgT, int G>
+// Learned proposal, FP32: the lanes waiting for a direction are ranked
+// (mbcnt over the ballot) and evaluated 16 at a time on the matrix cores;
+// their features go through a per-wave LDS tile into the B operand, the 40
+// outputs per sample come back through a second tile.  Must be called with
+// the whole wave active.
+template <typename ImgT, int G>
+__device__ __forceinline__ void resolve_wave(const View<float, ImgT, G> &v, Lane<float> &ln, Tally &ty,
+                                             const bf16x4 *Wf, const float *bias, uint16_t *feat, float *stage,
+                                             int lane)
+{
+    const unsigned long long need = __ballot(ln.mode == kNeedDir);
+    const int n = __popcll(need);
+    const bool mine = ln.mode == kNeedDir;
+    const int rank = (int)lanes_below(need);
+    float f[9];
+    if (mine) event_features(v, ln, !ln.emis_dir, f);
+    for (int sb = 0; 16 * sb < n; ++sb) {
+        const bool in_block = mine && (rank >> 4) == sb;
+        if (in_block) {
+            uint16_t *row = feat + 16 * (rank & 15);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) row[i] = i < 9 ? bf16_bits(f[i]) : (uint16_t)0;
+        }
+        wave_lds_sync();
+        bf16x4 x = *reinterpret_cast<const bf16x4 *>(feat + 16 * (lane & 15) + 4 * (lane >> 4));
+        f32x4 o[3];
+        mlp_forward16<false>(Wf, bias, x, lane, o);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int row = 16 * t + 4 * (lane >> 4) + i;
+                if (row < 40) stage[(lane & 15) * 41 + row] = o[t][i];
+            }
+        wave_lds_sync();
+        if (in_block) apply_proposal<DevSink<true, false>>(v, ln, ty, stage + (rank & 15) * 41);
+        wave_lds_sync();
+    }
+}
+
+// LEARN: learned proposal; HIST: plain run recording histories.  A variant
+// carries only the code (and registers) of its own features.
+template <typename Real, typename ImgT, int G, bool LEARN, bool HIST>
 __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, ImgT, G> a)
 {
     __shared__ Optics<Real> s_opt[kMaxLdsLambda];
@@ -67,10 +111,23 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
     }
     for (int i = threadIdx.x; i < v.n_ins; i += blockDim.x) s_ins[i] = a.ins[i];
     v.ins = s_ins;
+    // learned proposal (FP32): network fragments and biases in LDS, plus a
+    // feature tile [16][16] bf16 and an output tile [16][41] FP32 per wave
+    constexpr bool kMfma = LEARN && sizeof(Real) == 4;
+    __shared__ bf16x4 s_wf[kMfma ? kFragFwd * 64 : 1];
+    __shared__ float s_bias[kMfma ? kBiasFloats : 1];
+    __shared__ __attribute__((aligned(16))) uint16_t s_feat[kMfma ? (kBlock / 64) * 256 : 1];
+    __shared__ float s_stage[kMfma ? (kBlock / 64) * 16 * 41 : 1];
+    if constexpr (kMfma) {
+        const bf16x4 *wf = reinterpret_cast<const bf16x4 *>(a.mlp_frags);
+        for (int i = threadIdx.x; i < kFragFwd * 64; i += blockDim.x) s_wf[i] = wf[i];
+        for (int i = threadIdx.x; i < kBiasFloats; i += blockDim.x) s_bias[i] = a.mlp_bias[i];
+    }
     __syncthreads();
 
-    DevSink sink;
+    DevSink<LEARN, HIST> sink;
     const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
     Lane<Real> ln;
     ln.mode = kDead;
     ln.marching = false;
@@ -104,14 +161,27 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
                 uint64_t P = cur + rank;
                 uint32_t lam = (uint32_t)(P / a.count);
                 uint32_t id = (uint32_t)(a.first_id + P % a.count);
-                launch(v, ln, ty, lam, id, (uint32_t)P);
+                launch<DevSink<LEARN, HIST>>(v, ln, ty, lam, id, (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);
             cur += ndead < avail ? ndead : avail;
         }
-        // events of the lanes whose march ended (or that just launched)
-        if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
+        // events of the lanes whose march ended (or that just launched); with
+        // the learned proposal, the lanes parked for a direction get it here
+        for (;;) {
+            if (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) settle(v, ln, ty, sink);
+            if constexpr (!LEARN) {
+                break;
+            } else {
+                if (__ballot(ln.mode == kNeedDir) == 0) break;
+                if constexpr (kMfma) {
+                    resolve_wave(v, ln, ty, s_wf, s_bias, s_feat + wave * 256, s_stage + wave * 16 * 41, lane);
+                } else {
+                    if (ln.mode == kNeedDir) resolve_direction_scalar<DevSink<LEARN, HIST>>(v, ln, ty);
+                }
+            }
+        }
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;
@@ -188,7 +258,7 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
 template <typename Real, typename ImgT>
 __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real, ImgT> a)
 {
-    DevSink sink;
+    DevSink<false, false> sink;
     const int lane = __lane_id();
     Lane<Real> ln;
     ln.mode = kDead;
@@ -246,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
             uint32_t rank = lanes_below(dead);
             if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
-                launch(v, ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
+                launch<DevSink<false, false>>(v, ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);
@@ -277,7 +347,12 @@ hipError_t launch_batch_impl(const BatchArgs<Real, ImgT> &a, int grid, hipStream
 template <typename Real, typename ImgT, int G>
 hipError_t launch_transport_impl(const TransportArgs<Real, ImgT, G> &a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((transport_kernel<Real, ImgT, G>), dim3(grid), dim3(kBlock), 0, stream, a);
+    if (a.view.learned)
+        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, true, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+    else if (a.view.hist)
+        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, false, true>), dim3(grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, false, false>), dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -32,7 +32,13 @@ EXPORTS = [
     "mcrt_result_image", "mcrt_result_energy", "mcrt_result_stats", "mcrt_result_destroy",
     "mcrt_sim_info", "mcrt_last_error", "mcrt_microbench", "mcrt_microbench_error",
     "mcrt_batch_run_into", "mcrt_sim_set_tuning", "mcrt_autotune",
+    "mcrt_proposal_create", "mcrt_proposal_destroy", "mcrt_proposal_set_params",
+    "mcrt_proposal_get_params", "mcrt_proposal_get_weights", "mcrt_proposal_forward",
+    "mcrt_proposal_grad", "mcrt_sim_set_proposal", "mcrt_proposal_collect", "mcrt_histories_info",
+    "mcrt_histories_records", "mcrt_histories_samples", "mcrt_histories_destroy",
+    "mcrt_train_opts_default", "mcrt_proposal_train", "mcrt_proposal_eval",
 ]
+MLP_PARAMS = 7400
 
 
 class MCRTError(RuntimeError):
@@ -62,6 +68,17 @@ STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("init_seed", ctypes.c_uint64), ("init_scale", ctypes.c_float)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -127,6 +144,24 @@ def lib():
         "mcrt_sim_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "mcrt_autotune": (ctypes.c_int, [PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
                                          ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+        "mcrt_proposal_create": (ctypes.c_int, [P, ctypes.POINTER(MlpDesc), PP]),
+        "mcrt_proposal_destroy": (None, [P]),
+        "mcrt_proposal_set_params": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_proposal_get_params": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_proposal_get_weights": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_proposal_forward": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
+        "mcrt_proposal_grad": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, DP, P]),
+        "mcrt_sim_set_proposal": (ctypes.c_int, [P, P, ctypes.c_double]),
+        "mcrt_proposal_collect": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                                 ctypes.c_uint64, ctypes.c_int32, P, PP]),
+        "mcrt_histories_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int64), DP]),
+        "mcrt_histories_records": (ctypes.c_int, [P, P, ctypes.c_size_t, P, ctypes.c_size_t]),
+        "mcrt_histories_samples": (ctypes.c_int, [P, P, P, P, ctypes.c_size_t]),
+        "mcrt_histories_destroy": (None, [P]),
+        "mcrt_train_opts_default": (None, [ctypes.POINTER(TrainOpts)]),
+        "mcrt_proposal_train": (ctypes.c_int, [P, P, ctypes.POINTER(TrainOpts), DP]),
+        "mcrt_proposal_eval": (ctypes.c_int, [P, P, DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -188,9 +223,11 @@ class Context:
         _check(lib().mcrt_context_create(int(device), stream, ctypes.byref(h)))
         self.h = h
         self.device = device
-        self._objs = []
+        self._deps = weakref.WeakSet()  # proposals and histories (closed first)
 
     def close(self):
+        for d in list(getattr(self, "_deps", ())):
+            d.close()
         if self.h:
             lib().mcrt_context_destroy(self.h)
             self.h = None
@@ -308,6 +345,21 @@ class Sim:
         self.image_shapes = [(self.n_lambda, ins.npix[1], ins.npix[0]) for ins in scene.instruments]
         self.precision = precision
 
+    def set_proposal(self, prop: Optional["Proposal"], alpha: float = 0.2):
+        """Attach (or with None detach) a learned direction proposal."""
+        _check(lib().mcrt_sim_set_proposal(self.h, prop.h if prop is not None else None, float(alpha)))
+        self.proposal = prop
+
+    def collect(self, result: Result, n_per_lambda: int, seed: int = 0, max_events: int = 16,
+                first_id: int = 0, count: Optional[int] = None) -> "Histories":
+        """Plain run into result that also records per-event histories."""
+        if count is None:
+            count = n_per_lambda - first_id
+        h = ctypes.c_void_p()
+        _check(lib().mcrt_proposal_collect(self.h, int(n_per_lambda), int(first_id), int(count), int(seed),
+                                           int(max_events), result.h, ctypes.byref(h)), allow=(ELIMIT,))
+        return Histories(h, self.ctx)
+
     def set_tuning(self, chunk: int, waves_per_cu: int, threshold: int):
         t = Tuning(chunk, waves_per_cu, threshold, 0.0, 0)
         _check(lib().mcrt_sim_set_tuning(self.h, ctypes.byref(t)))
@@ -350,6 +402,118 @@ class Sim:
             if h:
                 fn(h)
                 setattr(self, name, None)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class Proposal:
+    """Learned direction proposal: network parameters on the device (FP32
+    master, bf16 fragments for the matrix cores, FP64 copy), Adam state."""
+
+    def __init__(self, ctx: Context, seed: int = 0, init_scale: float = 1.0, params=None):
+        self.ctx = ctx
+        self.h = None
+        d = MlpDesc(9, 64, 40, int(seed), float(init_scale))
+        h = ctypes.c_void_p()
+        _check(lib().mcrt_proposal_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        ctx._deps.add(self)
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, theta):
+        t = _f32(theta)
+        if t.size != MLP_PARAMS:
+            raise ValueError("expected 7400 parameters")
+        _check(lib().mcrt_proposal_set_params(self.h, t.ctypes.data, t.size))
+
+    def params(self) -> np.ndarray:
+        t = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().mcrt_proposal_get_params(self.h, t.ctypes.data, t.size))
+        return t
+
+    def weights_bf16(self) -> np.ndarray:
+        w = np.zeros(MLP_PARAMS, dtype=np.uint16)
+        _check(lib().mcrt_proposal_get_weights(self.h, w.ctypes.data, w.size))
+        return w
+
+    def forward(self, X) -> np.ndarray:
+        X = _f32(X).reshape(-1, 9)
+        out = np.zeros((X.shape[0], 40), dtype=np.float32)
+        _check(lib().mcrt_proposal_forward(self.h, X.ctypes.data, X.shape[0], out.ctypes.data))
+        return out
+
+    def grad(self, X, KP, C):
+        X, KP, C = _f32(X).reshape(-1, 9), _f32(KP).reshape(-1, 3), _f32(C).reshape(-1)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().mcrt_proposal_grad(self.h, X.ctypes.data, KP.ctypes.data, C.ctypes.data, X.shape[0],
+                                        ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train(self, hist: "Histories", epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
+              seed: int = 1) -> float:
+        o = TrainOpts()
+        lib().mcrt_train_opts_default(ctypes.byref(o))
+        o.epochs, o.batch, o.lr, o.seed = int(epochs), int(batch), float(lr), int(seed)
+        loss = ctypes.c_double()
+        _check(lib().mcrt_proposal_train(self.h, hist.h, ctypes.byref(o), ctypes.byref(loss)))
+        return loss.value
+
+    def eval(self, hist: "Histories") -> float:
+        loss = ctypes.c_double()
+        _check(lib().mcrt_proposal_eval(self.h, hist.h, ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mcrt_proposal_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Histories:
+    """Per-event records of a plain run and the training samples built from them."""
+
+    def __init__(self, h, ctx: Context):
+        self.h = h
+        ctx._deps.add(self)
+        n, e, ns, cs = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().mcrt_histories_info(h, ctypes.byref(n), ctypes.byref(e), ctypes.byref(ns), ctypes.byref(cs)))
+        self.n_packets, self.max_events, self.n_samples, self.weight_sum = n.value, e.value, ns.value, cs.value
+
+    def records(self):
+        rec = np.zeros((self.n_packets, self.max_events, 14))
+        tot = np.zeros(self.n_packets)
+        _check(lib().mcrt_histories_records(self.h, rec.ctypes.data, rec.size, tot.ctypes.data, tot.size))
+        return rec, tot
+
+    def samples(self):
+        n = self.n_samples
+        X = np.zeros((n, 9), dtype=np.float32)
+        KP = np.zeros((n, 3), dtype=np.float32)
+        C = np.zeros(n, dtype=np.float32)
+        if n:
+            _check(lib().mcrt_histories_samples(self.h, X.ctypes.data, KP.ctypes.data, C.ctypes.data, n))
+        return X, KP, C
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mcrt_histories_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _handles(objs):

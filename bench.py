@@ -40,7 +40,7 @@ def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_04702_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.startswith("transport") or f in ("internal.h", "det_math.h"):
+        if f.startswith("transport") or f in ("internal.h", "det_math.h", "proposal.h"):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -164,7 +164,7 @@ def bench_learned(args):
     # 2. training
     prop = mcrt.Proposal(ctx, seed=7, init_scale=1.0)
     loss0 = prop.eval(hist)
-    _, t_train = timed(lambda: prop.train(hist, epochs=args.epochs, batch=8192, lr=1e-3, seed=3))
+    _, t_train = timed(lambda: prop.train(hist, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=3))
     loss1 = prop.eval(hist)
     log(f"trained {args.epochs} epochs in {t_train:.2f} s: loss {loss0:.4f} -> {loss1:.4f}")
     hist.close()
@@ -184,8 +184,14 @@ def bench_learned(args):
             log(f"{'learned' if learned else 'plain'} ids [{b0}, {b0 + cnt}) of {n_per_lambda}/lambda done")
         img = _image_cube(res, n_ins)
         e = res.energy()
+        st = res.stats()
         res.close()
+        per = {f: st[f] / max(st["packets"], 1) for f in ("events", "prop_cells", "locate_cells", "peel_cells",
+                                                          "peel_adds")}
+        counters[("learned" if learned else "plain")] = per
         return img, kms / 1e3, e
+
+    counters = {}
 
     # 3. reference in two halves, learned run, plain run of equal transport time
     half = n_ref // 2
@@ -213,14 +219,16 @@ def bench_learned(args):
                                   "instrument) with the learned vMF-mixture direction proposal",
                       "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
                       "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
-                      "alpha": 0.2, "epochs": args.epochs, "max_events": args.max_events},
+                      "alpha": 0.2, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                      "max_events": args.max_events},
            "learned_vs_plain": {"rms_learned": rms_l, "rms_plain": rms_p, "t_learned_s": t_learned,
                                 "t_plain_s": t_plain, "rms2_t_learned": rms_l ** 2 * t_learned,
                                 "rms2_t_plain": rms_p ** 2 * t_plain, "fom_gain": fom_l / fom_p,
                                 "flux_learned_over_ref": tot_l / tot_r, "flux_plain_over_ref": tot_p / tot_r,
                                 "reference_noise_fraction": noise / ref2,
                                 "collect_s": t_collect, "train_s": t_train, "loss_before": loss0,
-                                "loss_after": loss1, "energy_balance_learned":
+                                "loss_after": loss1, "counters_per_packet": counters,
+                                "energy_balance_learned":
                                     abs(e_learned[0] - e_learned[1] - e_learned[2] - e_learned[3]) / e_learned[0]}}
     prop.close()
     sim.close()
@@ -309,6 +317,8 @@ def main():
     ap.add_argument("--learned-packets", type=int, default=100_000_000, help="torus-learned: learned packets")
     ap.add_argument("--ref-packets", type=int, default=1_000_000_000, help="torus-learned: reference packets")
     ap.add_argument("--epochs", type=int, default=2, help="torus-learned: training epochs")
+    ap.add_argument("--batch", type=int, default=8192, help="torus-learned: samples per Adam step")
+    ap.add_argument("--lr", type=float, default=1e-3, help="torus-learned: Adam learning rate")
     ap.add_argument("--max-events", type=int, default=16, help="torus-learned: recorded events per packet")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")

@@ -37,8 +37,7 @@ struct HostSink {
     {
         if (v != 0.0) *p += v;
     }
-    void pixel(float *p, float v) { *p += v; }
-    void pixel(double *p, double v) { *p += v; }
+    template <typename L, typename T> void pixel(L &, T *images, long long idx, T v) { images[idx] += v; }
 };
 } // namespace
 
@@ -187,8 +186,8 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
             Lane<Real> ln{};
             launch<HostSink>(v, ln, ty, (uint32_t)l, (uint32_t)i, (uint32_t)((uint64_t)l * count + (i - first)));
             settle(v, ln, ty, sink);
-            while (ln.mode != kDead) {
-                if (ln.mode == kNeedDir) {
+            while (ln.mode != kDead || ln.parked) {
+                if (ln.parked) {
                     resolve_direction_scalar<HostSink>(v, ln, ty);
                     if (!ln.marching) settle(v, ln, ty, sink);
                     continue;

@@ -718,9 +718,21 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     mcrt_sim *s0 = sims[0];
     hipStream_t st = s0->ctx->stream;
     const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? s0->opt.chunk : 256);
+    // Queue order: most expensive model first (longest-processing-time order,
+    // cost ~ packets x wavelengths x cells along the axes), so the cheap
+    // models fill the tail of the launch.  The model index in the random
+    // streams stays the position in the caller's list.
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+    auto cost = [&](int i) {
+        const mcrt_grid *g = sims[i]->medium->grid;
+        return (double)npl[i] * sims[i]->medium->n_lambda * (double)(g->n[0] + g->n[1] + g->n[2]);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
     std::vector<ModelDesc<Real, ImgT>> md((size_t)n);
     uint64_t chunk0 = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int q = 0; q < n; ++q) {
+        const int i = order[(size_t)q];
         mcrt_sim *s = sims[i];
         const mcrt_medium *m = s->medium;
         const mcrt_grid *g = m->grid;
@@ -729,7 +741,7 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
             optics[l] = Optics<Real>{(Real)m->kappa[l], (Real)m->albedo[l], (Real)m->g[l],
                                      (Real)(s->source->L[l] / (double)npl[i])};
         HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
-        ModelDesc<Real, ImgT> &d = md[(size_t)i];
+        ModelDesc<Real, ImgT> &d = md[(size_t)q];
         d = ModelDesc<Real, ImgT>{};
         View<Real, ImgT, kCartesian> &v = d.view;
         for (int c = 0; c < 3; ++c) {

@@ -31,8 +31,11 @@ enum Mode : int {
     kLocate = 3,    // second march to the forced interaction point
     kPeelScat = 4,  // scattering peel-off march towards instrument j
     kLaunched = 5,  // launched, first march not yet begun
-    kNeedDir = 6,   // waiting for the learned proposal to pick the next direction
 };
+// A lane waiting for the learned proposal to pick its next direction has
+// mode kDead with `parked` set: the event loop stops there exactly as for a
+// finished packet, and the kernel hands it to the proposal instead of
+// refilling it.
 
 constexpr int kMlpParams = 7400; // 9 -> 64 -> 64 -> 40
 constexpr int kHistFloats = 14;  // features (9), new direction (3), luminosity, flux so far
@@ -182,7 +185,9 @@ template <typename Real> struct Lane {
     uint32_t slot;      // packet index in the launch (histories)
     Real rho_star;      // density of the interaction cell
     Real flux;          // image flux produced so far (histories)
-    bool marching, found, dropped, emis_dir;
+    long long pix;      // pending pixel add (index, -1: none) for the wave-level combine
+    Real pval;
+    bool marching, found, dropped, emis_dir, parked;
 };
 
 // Per-axis fields are separate scalars (not arrays): stores through a
@@ -839,6 +844,7 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
         qv = qv + o[j] * fj;
     }
     Real q = v.alpha * pphys + (Real(1) - v.alpha) * qv;
+    ln.parked = false;
     ln.L = (emis ? ln.L0 : ln.L) * (pphys / q);
     ln.k[0] = kp[0];
     ln.k[1] = kp[1];
@@ -861,7 +867,8 @@ template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 {
     if (learned_on<Sink>(v)) {
-        ln.mode = kNeedDir;
+        ln.mode = kDead;
+        ln.parked = true;
         ln.emis_dir = false;
         ln.marching = false;
         return;
@@ -891,7 +898,8 @@ template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void emission_done(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
     if (learned_on<Sink>(v) && v.src_type != kExpDisk) {
-        ln.mode = kNeedDir;
+        ln.mode = kDead;
+        ln.parked = true;
         ln.emis_dir = true;
         ln.marching = false;
         return;
@@ -914,6 +922,7 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.slot = slot;
     ln.flux = Real(0);
     ln.emis_dir = false;
+    ln.parked = false;
     ln.opt = v.optics[lam];
     Stream st = stream_of(v, ln);
     if (v.src_type == kExpDisk) {
@@ -979,7 +988,7 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
             if (px >= Real(0) && px < Real(in.nx) && py >= Real(0) && py < Real(in.ny)) {
                 long long idx = in.offset + ((long long)ln.lam * in.ny + (long long)py) * in.nx + (long long)px;
                 Real val = ln.wpeel * Math<Real>::e_exp(-ln.tau);
-                sink.pixel(v.images + idx, (ImgT)val);
+                sink.pixel(ln, v.images, idx, (ImgT)val);
                 if (hist_on<Sink>(v)) ln.flux = ln.flux + val * in.inv4pid2;
                 ty.peel_adds++;
             }
@@ -1034,11 +1043,7 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
 template <typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void settle(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
-    if constexpr (Sink::kLearn) {
-        while (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) finish_march(v, ln, ty, sink);
-    } else {
-        while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
-    }
+    while (!ln.marching && ln.mode != kDead) finish_march(v, ln, ty, sink);
 }
 
 // One sample at a time: features, network, proposal (host simulator and the

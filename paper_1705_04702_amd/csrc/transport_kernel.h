@@ -34,9 +34,36 @@ template <bool LEARN, bool HIST> struct DevSink {
     {
         if (v != 0.0) unsafeAtomicAdd(p, v);
     }
-    __device__ __forceinline__ void pixel(float *p, float v) { unsafeAtomicAdd(p, v); }
-    __device__ __forceinline__ void pixel(double *p, double v) { unsafeAtomicAdd(p, v); }
+    // Pixel adds are held in the lane (one pending add) and combined across
+    // the wave at the next uniform point (flush_pixels); a second add before
+    // that goes out directly.
+    template <typename Real, typename T>
+    __device__ __forceinline__ void pixel(Lane<Real> &ln, T *images, long long idx, T v)
+    {
+        if (ln.pix >= 0) unsafeAtomicAdd(images + ln.pix, (T)ln.pval);
+        ln.pix = idx;
+        ln.pval = (Real)v;
+    }
 };
+
+// Wave-level combine of the pending pixel adds: the lanes whose pixel equals
+// the first pending lane's pixel are summed across the wave and added once
+// (a point source's emission peel-offs all land in one pixel per
+// wavelength); the other lanes add their own.  Whole wave active.
+template <typename Real, typename ImgT>
+__device__ __forceinline__ void flush_pixels(Lane<Real> &ln, ImgT *images, int lane)
+{
+    const unsigned long long m = __ballot(ln.pix >= 0);
+    if (m == 0) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const long long key = __shfl(ln.pix, leader, 64);
+    const bool same = ln.pix == key;
+    ImgT s = same ? (ImgT)ln.pval : (ImgT)0;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == leader) unsafeAtomicAdd(images + key, s);
+    else if (ln.pix >= 0 && !same) unsafeAtomicAdd(images + ln.pix, (ImgT)ln.pval);
+    ln.pix = -1;
+}
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
 {
@@ -65,9 +92,9 @@ __device__ __forceinline__ void resolve_wave(const View<float, ImgT, G> &v, Lane
                                              const bf16x4 *Wf, const float *bias, uint16_t *feat, float *stage,
                                              int lane)
 {
-    const unsigned long long need = __ballot(ln.mode == kNeedDir);
+    const unsigned long long need = __ballot(ln.parked);
     const int n = __popcll(need);
-    const bool mine = ln.mode == kNeedDir;
+    const bool mine = ln.parked;
     const int rank = (int)lanes_below(need);
     float f[9];
     if (mine) event_features(v, ln, !ln.emis_dir, f);
@@ -131,6 +158,8 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
     Lane<Real> ln;
     ln.mode = kDead;
     ln.marching = false;
+    ln.parked = false;
+    ln.pix = -1;
     Tally ty = {};
     uint64_t cur = 0, end = 0;
     bool exhausted = false;
@@ -140,7 +169,7 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
         // refilled lane only launches here, its events run below
         bool launched = false;
         for (;;) {
-            unsigned long long dead = __ballot(ln.mode == kDead && !launched);
+            unsigned long long dead = __ballot(ln.mode == kDead && !ln.parked && !launched);
             if (dead == 0 || exhausted) break;
             if (cur >= end) {
                 unsigned long long c = 0;
@@ -157,7 +186,7 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
             }
             uint64_t avail = end - cur;
             uint32_t rank = lanes_below(dead);
-            if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
+            if (ln.mode == kDead && !ln.parked && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
                 uint32_t lam = (uint32_t)(P / a.count);
                 uint32_t id = (uint32_t)(a.first_id + P % a.count);
@@ -170,18 +199,19 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
         // events of the lanes whose march ended (or that just launched); with
         // the learned proposal, the lanes parked for a direction get it here
         for (;;) {
-            if (!ln.marching && ln.mode != kDead && ln.mode != kNeedDir) settle(v, ln, ty, sink);
+            if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
             if constexpr (!LEARN) {
                 break;
             } else {
-                if (__ballot(ln.mode == kNeedDir) == 0) break;
+                if (__ballot(ln.parked) == 0) break;
                 if constexpr (kMfma) {
                     resolve_wave(v, ln, ty, s_wf, s_bias, s_feat + wave * 256, s_stage + wave * 16 * 41, lane);
                 } else {
-                    if (ln.mode == kNeedDir) resolve_direction_scalar<DevSink<LEARN, HIST>>(v, ln, ty);
+                    if (ln.parked) resolve_direction_scalar<DevSink<LEARN, HIST>>(v, ln, ty);
                 }
             }
         }
+        flush_pixels(ln, v.images, lane);
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;
@@ -263,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
     Lane<Real> ln;
     ln.mode = kDead;
     ln.marching = false;
+    ln.pix = -1;
     Tally ty = {};
     int cur_model = -1, pend_model = -1;
     View<Real, ImgT, 0> v{};
@@ -323,6 +354,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
             cur += ndead < avail ? ndead : avail;
         }
         if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
+        flush_pixels(ln, v.images, lane);
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;

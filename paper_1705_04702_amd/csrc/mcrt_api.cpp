@@ -772,6 +772,8 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
         v.model = (uint32_t)i;
         d.optics = (const Optics<Real> *)s->d_optics;
         d.ins = (const InsDesc<Real> *)s->d_ins;
+        v.optics = d.optics; // the batch kernel reads optics and frames from global memory
+        v.ins = d.ins;
         d.count = npl[i];
         d.first_id = 0;
         d.total = npl[i] * (uint64_t)m->n_lambda;

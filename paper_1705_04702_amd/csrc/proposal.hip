@@ -187,7 +187,7 @@ __device__ __forceinline__ void split_bf16(f32x4 x, bf16x4 &hi, bf16x4 &lo)
 
 __global__ void __launch_bounds__(64) grad_kernel(GradArgs g)
 {
-    __shared__ bf16x4 s_wf[kFragAll * 64];
+    __shared__ __attribute__((aligned(16))) bf16x4 s_wf[kFragAll * 64];
     __shared__ float s_bias[kBiasFloats];
     // bf16 tiles are read 4 values (8 bytes) at a time: 16-byte aligned
     __shared__ __attribute__((aligned(16))) uint16_t s_xt[16 * kSX];
@@ -204,8 +204,11 @@ __global__ void __launch_bounds__(64) grad_kernel(GradArgs g)
     __shared__ __attribute__((aligned(16))) uint16_t s_dz1_lo[64 * kSZ];
 
     const int lane = threadIdx.x;
-    const bf16x4 *wf = reinterpret_cast<const bf16x4 *>(g.frags);
-    for (int i = lane; i < kFragAll * 64; i += 64) s_wf[i] = wf[i];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(g.frags);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_wf);
+        for (int i = lane; i < kFragAll * 32; i += 64) dst[i] = src[i];
+    }
     for (int i = lane; i < kBiasFloats; i += 64) s_bias[i] = g.bias[i];
     __syncthreads();
 
@@ -411,19 +414,29 @@ hipError_t launch_proposal_grad(const GradArgs &g, int waves, hipStream_t stream
     return hipGetLastError();
 }
 
-// Sum of the per-wave gradients (fixed order), then optionally one Adam step
-// on the FP32 master parameters.  step >= 1 is the Adam time step.
-__global__ void adam_kernel(const float *partial, int waves, const double *loss_partial, AdamArgs a)
+// Sum of the per-wave gradients in a fixed order (32 parameters x 8 wave
+// slices per workgroup, slices combined in index order), then optionally one
+// Adam step on the FP32 master parameters.  step >= 1 is the Adam time step.
+__global__ void __launch_bounds__(256) adam_kernel(const float *partial, int waves, const double *loss_partial,
+                                                   AdamArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && a.loss_out) {
+    __shared__ float red[8][32];
+    const int c = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + c;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
         double l = 0.0;
         for (int w = 0; w < waves; ++w) l += loss_partial[w];
         *a.loss_out = l;
     }
-    if (i >= kMlpParams) return;
-    float gsum = 0.0f;
-    for (int w = 0; w < waves; ++w) gsum += partial[(int64_t)w * kGradStride + i];
+    float s = 0.0f;
+    if (i < kMlpParams)
+        for (int w = j; w < waves; w += 8) s += partial[(int64_t)w * kGradStride + i];
+    red[j][c] = s;
+    __syncthreads();
+    if (j != 0 || i >= kMlpParams) return;
+    float gsum = red[0][c];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) gsum += red[k][c];
     if (a.grad_out) a.grad_out[i] = gsum;
     if (!a.update) return;
     float m = a.b1 * a.m[i] + (1.0f - a.b1) * gsum;
@@ -438,7 +451,7 @@ __global__ void adam_kernel(const float *partial, int waves, const double *loss_
 hipError_t launch_proposal_adam(const float *partial, int waves, const double *loss_partial, const AdamArgs &a,
                                 hipStream_t stream)
 {
-    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, stream, partial, waves,
+    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 31) / 32), dim3(256), 0, stream, partial, waves,
                        loss_partial, a);
     return hipGetLastError();
 }

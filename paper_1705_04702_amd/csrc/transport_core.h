@@ -31,6 +31,7 @@ enum Mode : int {
     kLocate = 3,    // second march to the forced interaction point
     kPeelScat = 4,  // scattering peel-off march towards instrument j
     kLaunched = 5,  // launched, first march not yet begun
+    kNewDir = 6,    // direction chosen by the learned proposal, propagation not yet begun
 };
 // A lane waiting for the learned proposal to pick its next direction has
 // mode kDead with `parked` set: the event loop stops there exactly as for a
@@ -786,9 +787,10 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
     }
     Stream st = stream_of(v, ln);
     const bool emis = ln.emis_dir;
+    // u1: slot 5 (emission) or 8e+1; u2, u3: slots 6, 7 or 8e+2, 8e+3 (one Philox block)
     Real u1 = st.template slot<Real>(emis ? 5u : (uint32_t)(8 * ln.e + 1));
-    Real u2 = st.template slot<Real>(emis ? 6u : (uint32_t)(8 * ln.e + 2));
-    Real u3 = st.template slot<Real>(emis ? 7u : (uint32_t)(8 * ln.e + 3));
+    Real u2, u3;
+    st.template pair<Real>(emis ? 3u : (uint32_t)(4 * ln.e + 1), u2, u3);
     Real kp[3];
     if (u3 < v.alpha) {
         if (emis) {
@@ -849,16 +851,9 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
     ln.k[0] = kp[0];
     ln.k[1] = kp[1];
     ln.k[2] = kp[2];
-    if (!emis) {
-        ln.e = ln.e + 1;
-        if (ln.e > v.event_cap) {
-            ty.truncated += (double)ln.L;
-            ty.capped++;
-            end_packet<Sink>(v, ln);
-            return;
-        }
-    }
-    begin_prop(v, ln);
+    if (!emis) ln.e = ln.e + 1;
+    ln.mode = kNewDir; // the event loop starts the propagation (or applies the cap)
+    ln.marching = false;
 }
 
 // Scattering: new HG direction (or the learned proposal), then the next
@@ -974,6 +969,16 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
     if (ln.mode == kLaunched) {
         if (v.n_ins > 0) begin_peel(v, ln, 0, true);
         else emission_done<Sink>(v, ln);
+        return;
+    }
+    if (Sink::kLearn && ln.mode == kNewDir) {
+        if (ln.e > v.event_cap) {
+            ty.truncated += (double)ln.L;
+            ty.capped++;
+            end_packet<Sink>(v, ln);
+            return;
+        }
+        begin_prop(v, ln);
         return;
     }
     if (ln.mode == kPeelEmit || ln.mode == kPeelScat) {

@@ -125,7 +125,7 @@ __device__ __forceinline__ void resolve_wave(const View<float, ImgT, G> &v, Lane
 // LEARN: learned proposal; HIST: plain run recording histories.  A variant
 // carries only the code (and registers) of its own features.
 template <typename Real, typename ImgT, int G, bool LEARN, bool HIST>
-__global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, ImgT, G> a)
+__device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G> &a)
 {
     __shared__ Optics<Real> s_opt[kMaxLdsLambda];
     __shared__ InsDesc<Real> s_ins[kMaxIns];
@@ -244,17 +244,19 @@ __global__ void __launch_bounds__(kBlock) transport_kernel(TransportArgs<Real, I
     }
 }
 
-// Copies a wave-uniform struct through readfirstlane, so the compiler keeps
-// it in scalar registers.
-template <typename T> __device__ __forceinline__ T uniform_copy(const T &src)
+// FP32 production kernels: at most 168 VGPRs, three waves per SIMD.
+template <int G, bool LEARN, bool HIST>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+transport_kernel_f32(TransportArgs<float, float, G> a)
 {
-    static_assert(sizeof(T) % 4 == 0, "word-sized struct expected");
-    T dst;
-    const int *s = reinterpret_cast<const int *>(&src);
-    int *d = reinterpret_cast<int *>(&dst);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
-    return dst;
+    transport_body<float, float, G, LEARN, HIST>(a);
+}
+
+// FP64 validation kernels (the scalar FP64 network needs more registers).
+template <int G, bool LEARN, bool HIST>
+__global__ void __launch_bounds__(kBlock) transport_kernel_f64(TransportArgs<double, double, G> a)
+{
+    transport_body<double, double, G, LEARN, HIST>(a);
 }
 
 template <typename Real, typename ImgT, int G>
@@ -296,7 +298,12 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
     ln.pix = -1;
     Tally ty = {};
     int cur_model = -1, pend_model = -1;
-    View<Real, ImgT, 0> v{};
+    // The current model's view is read through a constant-address-space
+    // pointer: its fields become scalar loads the compiler may repeat instead
+    // of holding ~60 values in registers across the event loop.
+    typedef const View<Real, ImgT, 0> __attribute__((address_space(4))) CView;
+    CView *vc = (CView *)&a.models[0].view;
+    auto V = [&]() -> const View<Real, ImgT, 0> & { return *(const View<Real, ImgT, 0> *)vc; };
     uint64_t count = 1, first_id = 0;
     uint64_t cur = 0, end = 0, pend_cur = 0, pend_end = 0;
     bool exhausted = false;
@@ -332,9 +339,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
                         flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
                     cur_model = pend_model;
                     const ModelDesc<Real, ImgT> &m = a.models[cur_model];
-                    v = uniform_copy(m.view);
-                    v.optics = m.optics;
-                    v.ins = m.ins;
+                    vc = (CView *)&a.models[cur_model].view;
                     count = m.count;
                     first_id = m.first_id;
                 }
@@ -347,20 +352,20 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
             uint32_t rank = lanes_below(dead);
             if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
-                launch<DevSink<false, false>>(v, ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
+                launch<DevSink<false, false>>(V(), ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);
             cur += ndead < avail ? ndead : avail;
         }
-        if (!ln.marching && ln.mode != kDead) settle(v, ln, ty, sink);
-        flush_pixels(ln, v.images, lane);
+        if (!ln.marching && ln.mode != kDead) settle(V(), ln, ty, sink);
+        flush_pixels(ln, V().images, lane);
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;
         }
         for (;;) {
-            if (ln.marching) march_step(v, ln, ty, sink);
+            if (ln.marching) march_step(V(), ln, ty, sink);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;
@@ -379,12 +384,21 @@ hipError_t launch_batch_impl(const BatchArgs<Real, ImgT> &a, int grid, hipStream
 template <typename Real, typename ImgT, int G>
 hipError_t launch_transport_impl(const TransportArgs<Real, ImgT, G> &a, int grid, hipStream_t stream)
 {
-    if (a.view.learned)
-        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, true, false>), dim3(grid), dim3(kBlock), 0, stream, a);
-    else if (a.view.hist)
-        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, false, true>), dim3(grid), dim3(kBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL((transport_kernel<Real, ImgT, G, false, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+    if constexpr (sizeof(Real) == 4) {
+        if (a.view.learned)
+            hipLaunchKernelGGL((transport_kernel_f32<G, true, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+        else if (a.view.hist)
+            hipLaunchKernelGGL((transport_kernel_f32<G, false, true>), dim3(grid), dim3(kBlock), 0, stream, a);
+        else
+            hipLaunchKernelGGL((transport_kernel_f32<G, false, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+    } else {
+        if (a.view.learned)
+            hipLaunchKernelGGL((transport_kernel_f64<G, true, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+        else if (a.view.hist)
+            hipLaunchKernelGGL((transport_kernel_f64<G, false, true>), dim3(grid), dim3(kBlock), 0, stream, a);
+        else
+            hipLaunchKernelGGL((transport_kernel_f64<G, false, false>), dim3(grid), dim3(kBlock), 0, stream, a);
+    }
     return hipGetLastError();
 }
 

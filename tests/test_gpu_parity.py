@@ -253,3 +253,49 @@ def test_concurrent_run_is_busy(ctx):
         r2.close()
     finally:
         sim.close()
+
+
+def test_full_size_disk_in_the_bench_launch_configuration(ctx):
+    """The disk workload at full size in bench.py's launch (ids [0, 1e6) of
+    all 64 wavelengths, 6.4e7 packets, FP32): properties that hold at any
+    size -- energy balance, packet count, two half-ranges adding up to the
+    whole -- and the absorbed total per wavelength against the oracle's
+    estimate from a packet subset (4 sigma)."""
+    sc = scenes.disk()
+    N = 10_000_000
+    B = 1_000_000
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    try:
+        say("full-size disk launch: ids [0, 1e6) x 64 wavelengths")
+        whole = sim.run(N, 0, 0, B)
+        halves = sim.new_result()
+        sim.run_into(halves, N, 0, 0, B // 2)
+        sim.run_into(halves, N, 0, B // 2, B - B // 2)
+        e = whole.energy()
+        assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+        st = whole.stats()
+        assert st["packets"] == B * sc.n_lambda and st["capped"] == 0
+        np.testing.assert_allclose(halves.energy(), e, rtol=1e-6)
+        tw, th = whole.table(), halves.table()
+        per_l_w, per_l_h = tw.sum(axis=0), th.sum(axis=0)
+        np.testing.assert_allclose(per_l_h, per_l_w, rtol=1e-5)
+        # oracle estimate of the absorbed luminosity per packet on 4 of the
+        # wavelengths (one-wavelength copies of the scene, own streams): K
+        # independent batches give the mean and its standard error
+        K, n_b = 16, 16
+        bad = 0
+        for ell in (0, 21, 42, 63):
+            sub = type(sc)(**{**sc.__dict__})
+            for f in ("lambdas", "kappa", "albedo", "hg_g", "lum"):
+                setattr(sub, f, np.ascontiguousarray(getattr(sc, f)[ell:ell + 1]))
+            means = np.array([oracle.run(sub, N, seed=7, first_id=k * n_b, count=n_b)["energy"][1] / n_b
+                              for k in range(K)])
+            m, se = means.mean(), means.std(ddof=1) / np.sqrt(K)
+            g_mean = per_l_w[ell] / B
+            say(f"lambda {ell}: gpu {g_mean:.6e} per packet, oracle {m:.6e} +- {se:.2e}")
+            bad += abs(g_mean - m) > 4.5 * se + 1e-9 * abs(m)
+        assert bad == 0
+        for r in (whole, halves):
+            r.close()
+    finally:
+        sim.close()

@@ -81,7 +81,8 @@ def bench_batch(args):
     from paper_1705_04702_amd import mcrt, scenes
     models = scenes.batch(256, seed=4)
     ctx = mcrt.Context(0)
-    sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32) for m in models]
+    sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32, chunk=args.chunk or None, waves_per_cu=args.waves_per_cu or None,
+                     threshold=args.threshold or None) for m in models]
     npl = [m.n_packets for m in models]
     tuning = None
     if args.autotune:
@@ -317,7 +318,7 @@ def main():
     ap.add_argument("--learned-packets", type=int, default=100_000_000, help="torus-learned: learned packets")
     ap.add_argument("--ref-packets", type=int, default=1_000_000_000, help="torus-learned: reference packets")
     ap.add_argument("--epochs", type=int, default=2, help="torus-learned: training epochs")
-    ap.add_argument("--batch", type=int, default=8192, help="torus-learned: samples per Adam step")
+    ap.add_argument("--batch", type=int, default=16384, help="torus-learned: samples per Adam step")
     ap.add_argument("--lr", type=float, default=1e-3, help="torus-learned: Adam learning rate")
     ap.add_argument("--max-events", type=int, default=16, help="torus-learned: recorded events per packet")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

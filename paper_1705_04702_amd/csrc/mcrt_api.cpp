@@ -940,12 +940,12 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         return rc;
     }
     cur.kernel_ms = ms;
-    const int chunks[] = {32, 64, 128, 256, 512};
+    const int chunks[] = {32, 64, 128, 256, 512, 1024, 2048};
     const int thresholds[] = {8, 16, 32, 48};
     const int waves[] = {8, 12, 16};
     for (int pass = 0; pass < 3 && !rc; ++pass) {
         const int *vals = pass == 0 ? chunks : pass == 1 ? thresholds : waves;
-        int nv = pass == 0 ? 5 : pass == 1 ? 4 : 3;
+        int nv = pass == 0 ? 7 : pass == 1 ? 4 : 3;
         for (int k = 0; k < nv; ++k) {
             mcrt_tuning t = cur;
             if (pass == 0) t.chunk = vals[k];
@@ -1367,9 +1367,9 @@ int mcrt_proposal_grad(mcrt_proposal *p, const float *X, const float *KP, const 
 void mcrt_train_opts_default(mcrt_train_opts *o)
 {
     if (!o) return;
-    o->epochs = 4;
-    o->batch = 8192;
-    o->lr = 2e-3f;
+    o->epochs = 2;
+    o->batch = 16384;
+    o->lr = 1e-3f;
     o->beta1 = 0.9f;
     o->beta2 = 0.999f;
     o->eps = 1e-8f;

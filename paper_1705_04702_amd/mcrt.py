@@ -453,7 +453,7 @@ class Proposal:
                                         ctypes.byref(loss), g.ctypes.data))
         return loss.value, g
 
-    def train(self, hist: "Histories", epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
+    def train(self, hist: "Histories", epochs: int = 2, batch: int = 16384, lr: float = 1e-3,
               seed: int = 1) -> float:
         o = TrainOpts()
         lib().mcrt_train_opts_default(ctypes.byref(o))

@@ -195,7 +195,8 @@ typedef struct {
 
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
 
-/* Autotuner: coordinate search over chunk {32..2048}, threshold {8..48} and
+/* Autotuner: coordinate search over chunk ({32..2048} for one sim,
+ * {256..16384} for a batch), threshold {8..48} and
  * waves per CU {8, 12, 16} with short trial runs of trial_packets[i] packets
  * per wavelength of each sim (one sim: the single-model kernel; several: the
  * batched kernel), keeping the fastest.  With cache_path (may be NULL) the

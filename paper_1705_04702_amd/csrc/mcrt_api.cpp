@@ -639,13 +639,17 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     a.count = count;
     a.first_id = first_id;
     a.total = count * (uint64_t)m->n_lambda;
-    a.chunk = (uint32_t)(s->opt.chunk > 0 ? s->opt.chunk : 256);
+    int wpc = s->opt.waves_per_cu > 0 ? s->opt.waves_per_cu : 16;
+    uint64_t waves = (uint64_t)s->ctx->n_cu * (uint64_t)wpc;
+    // default chunk: 256 packets, smaller for small launches so that every
+    // persistent wave gets work (never below 32)
+    uint64_t auto_chunk = a.total / waves;
+    auto_chunk = auto_chunk < 32 ? 32 : (auto_chunk > 256 ? 256 : auto_chunk);
+    a.chunk = (uint32_t)(s->opt.chunk > 0 ? (uint64_t)s->opt.chunk : auto_chunk);
     a.threshold = s->opt.threshold > 0 ? s->opt.threshold : 16;
     a.counter = r->d_counter;
     a.energy = r->d_energy;
     a.stats = r->d_stats;
-    int wpc = s->opt.waves_per_cu > 0 ? s->opt.waves_per_cu : 16;
-    uint64_t waves = (uint64_t)s->ctx->n_cu * (uint64_t)wpc;
     uint64_t chunks = (a.total + a.chunk - 1) / a.chunk;
     if (waves > chunks) waves = chunks;
     int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
@@ -717,7 +721,14 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
 {
     mcrt_sim *s0 = sims[0];
     hipStream_t st = s0->ctx->stream;
-    const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? s0->opt.chunk : 256);
+    // default chunk: large, since a wave drains its lanes whenever its next
+    // chunk belongs to another model -- total / (8 x waves), in 256 .. 16384
+    uint64_t total_packets = 0;
+    for (int i = 0; i < n; ++i) total_packets += npl[i] * (uint64_t)sims[i]->medium->n_lambda;
+    const int wpc0 = s0->opt.waves_per_cu > 0 ? s0->opt.waves_per_cu : 16;
+    uint64_t auto_chunk = total_packets / (32ull * (uint64_t)s0->ctx->n_cu * (uint64_t)wpc0);
+    auto_chunk = auto_chunk < 256 ? 256 : (auto_chunk > 16384 ? 16384 : auto_chunk);
+    const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? (uint64_t)s0->opt.chunk : auto_chunk);
     // Queue order: most expensive model first (longest-processing-time order,
     // cost ~ packets x wavelengths x cells along the axes), so the cheap
     // models fill the tail of the launch.  The model index in the random
@@ -940,7 +951,11 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         return rc;
     }
     cur.kernel_ms = ms;
-    const int chunks[] = {32, 64, 128, 256, 512, 1024, 2048};
+    // batches favour large chunks (a wave drains when its next chunk belongs
+    // to another model)
+    const int chunks_single[] = {32, 64, 128, 256, 512, 1024, 2048};
+    const int chunks_batch[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+    const int *chunks = n == 1 ? chunks_single : chunks_batch;
     const int thresholds[] = {8, 16, 32, 48};
     const int waves[] = {8, 12, 16};
     for (int pass = 0; pass < 3 && !rc; ++pass) {

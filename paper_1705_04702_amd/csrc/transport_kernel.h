@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
             uint32_t rank = lanes_below(dead);
             if (ln.mode == kDead && !launched && (uint64_t)rank < avail) {
                 uint64_t P = cur + rank;
-                launch<DevSink<false, false>>(V(), ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
+                launch<decltype(sink)>(V(), ln, ty, (uint32_t)(P / count), (uint32_t)(first_id + P % count), (uint32_t)P);
                 launched = true;
             }
             uint64_t ndead = (uint64_t)__popcll(dead);

@@ -97,7 +97,7 @@ def test_autotune_and_cache(ctx, tmp_path):
         t1 = mcrt.autotune(sims, [max(1, p // 4) for p in packets], seed=3, cache_path=cache)
         say(f"autotune: {t1}")
         assert not t1["from_cache"]
-        assert t1["chunk"] in (32, 64, 128, 256, 512, 1024, 2048) and t1["threshold"] in (8, 16, 32, 48)
+        assert t1["chunk"] in (256, 512, 1024, 2048, 4096, 8192, 16384) and t1["threshold"] in (8, 16, 32, 48)
         assert t1["waves_per_cu"] in (8, 12, 16) and t1["kernel_ms"] > 0
         t2 = mcrt.autotune(sims, [1] * len(sims), seed=3, cache_path=cache)
         assert t2["from_cache"] and (t2["chunk"], t2["threshold"], t2["waves_per_cu"]) == \

@@ -133,3 +133,14 @@ def test_histories_match_oracle(name):
     np.testing.assert_array_equal(l["hist"], o["hist"])
     np.testing.assert_array_equal(l["hist_total"], o["hist_total"])
     np.testing.assert_array_equal(l["table"], o["table"])
+
+
+def test_learned_event_cap_matches_oracle():
+    sc = scenes.sphere(n=12, tau=4.0, albedo=0.95, npix=16)
+    sc.event_cap = 2
+    theta = scenes.init_mlp(5, scale=1.2)
+    o = oracle.run(sc, 600, seed=3, mlp=theta)
+    l = lanesim.run(sc, 600, seed=3, precision=1, mlp=theta)
+    np.testing.assert_array_equal(l["table"], o["table"])
+    np.testing.assert_array_equal(l["energy"], o["energy"])
+    assert l["stats"]["capped"] == o["stats"]["capped"] == 600

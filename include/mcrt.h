@@ -325,9 +325,11 @@ const char *mcrt_last_error(void);
  * access patterns).  kind: 0 random 4-byte gathers, 1 random FP64 atomic adds
  * (device scope), 2 random FP64 atomic adds (workgroup scope), 3 random FP32
  * atomic adds, 4 streaming copy, 5 FP64 atomic adds in runs of 4 consecutive
- * elements.  bytes = working-set size (>= 4096), n_ops = operations.  *rate
- * receives operations/s (bytes/s, read + written, for the copy).  Allocates
- * and frees its own buffers; synchronises the device.  Errors: MCRT_EINVAL,
+ * elements, 6 FP64 atomic adds by groups of 8 lanes on one 64-byte line, 7 the
+ * same by whole waves on 64 consecutive elements.  bytes = working-set size
+ * (>= 4096), n_ops = operations.  *rate receives operations/s (bytes/s,
+ * read + written, for the copy).  Allocates and frees its own buffers;
+ * synchronises the device.  Errors: MCRT_EINVAL,
  * MCRT_ENOMEM, MCRT_EDEVICE (message in mcrt_microbench_error()). */
 int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_ops, double *rate);
 const char *mcrt_microbench_error(void);

@@ -42,6 +42,21 @@ __global__ void atomic_f64_kernel(double *dst, uint64_t n, uint64_t iters)
     }
 }
 
+// GROUP consecutive lanes add to GROUP consecutive elements (one random
+// base per group and iteration): how the L2 handles atomics that arrive
+// together for one cache line.
+template <int GROUP>
+__global__ void atomic_f64_group_kernel(double *dst, uint64_t n, uint64_t iters)
+{
+    uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t gid = tid / GROUP;
+    int r = (int)(tid % GROUP);
+    for (uint64_t i = 0; i < iters; ++i) {
+        uint64_t base = (mix64(gid * iters + i) % (n / GROUP)) * GROUP;
+        __hip_atomic_fetch_add(dst + base + r, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __global__ void atomic_f32_kernel(float *dst, uint64_t n, uint64_t iters)
 {
     uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,12 +79,14 @@ extern "C" const char *mcrt_microbench_error(void) { return g_mb_err.c_str(); }
 // kind: 0 random 4-byte gathers, 1 random FP64 atomics (device scope),
 // 2 random FP64 atomics (workgroup scope), 3 random FP32 atomics (device
 // scope), 4 streaming copy (bytes read + written), 5 FP64 atomics (device
-// scope) in runs of 4 consecutive elements.  bytes = working set; n_ops =
+// scope) in runs of 4 consecutive elements, 6 FP64 atomics (device scope)
+// by groups of 8 lanes on 8 consecutive elements (one 64-byte line), 7 the
+// same by whole waves on 64 consecutive elements.  bytes = working set; n_ops =
 // operations (ignored for the copy).  *rate = operations/s (bytes/s for the
 // copy), timed with HIP events on the default stream.
 extern "C" int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_ops, double *rate)
 {
-    if (!rate || bytes < 4096 || kind < 0 || kind > 5) {
+    if (!rate || bytes < 4096 || kind < 0 || kind > 7) {
         g_mb_err = "microbench: bad arguments";
         return MCRT_EINVAL;
     }
@@ -120,6 +137,14 @@ extern "C" int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_
         case 5:
             hipLaunchKernelGGL((atomic_f64_kernel<__HIP_MEMORY_SCOPE_AGENT, 4>), dim3(grid), dim3(block), 0, 0,
                                (double *)buf, bytes / 8, iters);
+            break;
+        case 6:
+            hipLaunchKernelGGL((atomic_f64_group_kernel<8>), dim3(grid), dim3(block), 0, 0, (double *)buf, bytes / 8,
+                               iters);
+            break;
+        case 7:
+            hipLaunchKernelGGL((atomic_f64_group_kernel<64>), dim3(grid), dim3(block), 0, 0, (double *)buf,
+                               bytes / 8, iters);
             break;
         }
         (void)hipEventRecord(e1, 0);

@@ -182,7 +182,7 @@ def _dptr(a):
 
 
 MICROBENCH_KINDS = {"gather4": 0, "atomic_f64": 1, "atomic_f64_wg": 2, "atomic_f32": 3, "copy": 4,
-                    "atomic_f64_run4": 5}
+                    "atomic_f64_run4": 5, "atomic_f64_line8": 6, "atomic_f64_wave64": 7}
 
 
 def microbench(kind: str, nbytes: int, n_ops: int = 1 << 28, device: int = 0) -> float:

@@ -30,7 +30,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream)
 }
 
 struct Layout {
-    int n[3], bs[3], nb[3];
+    int n[3], bs[3], nb[3], sh[3];
     int bricked;
 };
 
@@ -41,8 +41,8 @@ __device__ __forceinline__ int64_t layout_store(const Layout &L, int64_t c)
     int iy = (int)((c / L.n[0]) % L.n[1]);
     int iz = (int)(c / ((int64_t)L.n[0] * L.n[1]));
     int brick = (ix >> L.bs[0]) + L.nb[0] * ((iy >> L.bs[1]) + L.nb[1] * (iz >> L.bs[2]));
-    int in = (ix & ((1 << L.bs[0]) - 1)) + ((iy & ((1 << L.bs[1]) - 1)) << L.bs[0]) +
-             ((iz & ((1 << L.bs[2]) - 1)) << (L.bs[0] + L.bs[1]));
+    int in = ((ix & ((1 << L.bs[0]) - 1)) << L.sh[0]) + ((iy & ((1 << L.bs[1]) - 1)) << L.sh[1]) +
+             ((iz & ((1 << L.bs[2]) - 1)) << L.sh[2]);
     return (int64_t)brick * 32 + in;
 }
 
@@ -62,13 +62,15 @@ __global__ void table_readback_kernel(const double *src, double *dst, int64_t n_
 }
 
 hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store, int n_lambda, const int *n,
-                                 const int *bs, const int *nb, int64_t cell0, int64_t ncell, hipStream_t stream)
+                                 const int *bs, const int *sh, const int *nb, int64_t cell0, int64_t ncell,
+                                 hipStream_t stream)
 {
     Layout L{};
     L.bricked = bs != nullptr;
     for (int a = 0; a < 3; ++a) {
         L.n[a] = n ? n[a] : 1;
         L.bs[a] = bs ? bs[a] : 0;
+        L.sh[a] = sh ? sh[a] : 0;
         L.nb[a] = nb ? nb[a] : 1;
     }
     int64_t total = ncell * n_lambda;

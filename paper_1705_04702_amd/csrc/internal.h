@@ -39,10 +39,10 @@ hipError_t launch_transport_f64o(const TransportArgs<double, double, 1> &a, int 
 // auxiliary kernels (aux_kernels.hip)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 // dst[(c - cell0) * n_lambda + l] = src[l * n_store + store(c)] for cells c in
-// [cell0, cell0 + ncell); store() is the bricked layout (bs, nb) of a
+// [cell0, cell0 + ncell); store() is the bricked layout (bs, sh, nb) of a
 // Cartesian grid with n cells per axis, or the identity when bs == NULL.
 hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store, int n_lambda,
-                                 const int *n, const int *bs, const int *nb, int64_t cell0,
+                                 const int *n, const int *bs, const int *sh, const int *nb, int64_t cell0,
                                  int64_t ncell, hipStream_t stream);
 template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);

@@ -110,13 +110,13 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         double cs[3];
         for (int a = 0; a < 3; ++a) cs[a] = (s->box[3 + a] - s->box[a]) / (double)v.n[a];
         long long ns;
-        choose_bricks(cs, v.n, v.bs, v.nb, ns);
+        choose_bricks(cs, v.n, v.bs, v.sh, v.nb, ns);
         v.n_store = ns;
         stored.assign((size_t)ns, 0.0f);
         for (int iz = 0; iz < v.n[2]; ++iz)
             for (int iy = 0; iy < v.n[1]; ++iy)
                 for (int ix = 0; ix < v.n[0]; ++ix)
-                    stored[(size_t)store_index_host(v.bs, v.nb, ix, iy, iz)] =
+                    stored[(size_t)store_index_host(v.bs, v.sh, v.nb, ix, iy, iz)] =
                         s->density[ix + (size_t)v.n[0] * (iy + (size_t)v.n[1] * iz)];
         v.density = stored.data();
     } else {
@@ -201,7 +201,7 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         long long sc = c;
         if (G == kCartesian) {
             int ix = (int)(c % v.n[0]), iy = (int)((c / v.n[0]) % v.n[1]), iz = (int)(c / ((int64_t)v.n[0] * v.n[1]));
-            sc = store_index_host(v.bs, v.nb, ix, iy, iz);
+            sc = store_index_host(v.bs, v.sh, v.nb, ix, iy, iz);
         }
         for (int l = 0; l < s->n_lambda; ++l) o->table[c * s->n_lambda + l] = table[(size_t)l * v.n_store + sc];
     }

@@ -121,7 +121,7 @@ struct mcrt_sim {
     long long image_elems = 0;
     mcrt_options opt{};
     int depth = 0, top_level = 0;
-    int bs[3] = {0, 0, 0}, nb[3] = {1, 1, 1}; // Cartesian brick layout
+    int bs[3] = {0, 0, 0}, nb[3] = {1, 1, 1}, sh[3] = {0, 0, 0}; // Cartesian brick layout
     long long n_store = 0;                     // stored cells per wavelength slice
     // device copies of the scene
     float *d_density = nullptr;
@@ -450,7 +450,7 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
     if (g->type == kCartesian) {
         double cs[3];
         for (int a = 0; a < 3; ++a) cs[a] = (g->box[3 + a] - g->box[a]) / (double)g->n[a];
-        choose_bricks(cs, g->n, s->bs, s->nb, s->n_store);
+        choose_bricks(cs, g->n, s->bs, s->sh, s->nb, s->n_store);
         if (o.brick[0] >= 0) {
             s->n_store = 32;
             for (int a = 0; a < 3; ++a) {
@@ -458,6 +458,7 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
                 s->nb[a] = (g->n[a] + (1 << s->bs[a]) - 1) >> s->bs[a];
                 s->n_store *= s->nb[a];
             }
+            default_shifts(s->bs, s->sh);
         }
         if (s->n_store >= (1ll << 31)) {
             delete s;
@@ -467,7 +468,7 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         for (int iz = 0; iz < g->n[2]; ++iz)
             for (int iy = 0; iy < g->n[1]; ++iy)
                 for (int ix = 0; ix < g->n[0]; ++ix)
-                    stored[(size_t)store_index_host(s->bs, s->nb, ix, iy, iz)] =
+                    stored[(size_t)store_index_host(s->bs, s->sh, s->nb, ix, iy, iz)] =
                         dens[ix + (size_t)g->n[0] * (iy + (size_t)g->n[1] * iz)];
         dens = stored.data();
     }
@@ -590,6 +591,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     View<Real, ImgT, G> &v = a.view;
     for (int c = 0; c < 3; ++c) {
         v.bs[c] = s->bs[c];
+        v.sh[c] = s->sh[c];
         v.nb[c] = s->nb[c];
         v.n[c] = g->n[c];
         v.lo[c] = (Real)g->box[c];
@@ -757,6 +759,7 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
         View<Real, ImgT, kCartesian> &v = d.view;
         for (int c = 0; c < 3; ++c) {
             v.bs[c] = s->bs[c];
+            v.sh[c] = s->sh[c];
             v.nb[c] = s->nb[c];
             v.n[c] = g->n[c];
             v.lo[c] = (Real)g->box[c];
@@ -1035,8 +1038,7 @@ int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count)
     if (rc) return rc;
     for (int64_t c0 = 0; c0 < nc; c0 += block) {
         int64_t n = std::min(block, nc - c0);
-        hipError_t e = launch_table_readback(res->d_table, tmp, s->n_store, nl, g->n, bricked ? s->bs : nullptr,
-                                             s->nb, c0, n, st);
+        hipError_t e = launch_table_readback(res->d_table, tmp, s->n_store, nl, g->n, bricked ? s->bs : nullptr, s->sh, s->nb, c0, n, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(out + c0 * nl, tmp, (size_t)n * nl * sizeof(double), hipMemcpyDefault, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -163,32 +163,47 @@ inline void build_top_table(const std::vector<int32_t> &node, int top_level, std
 }
 
 // Brick shape for the Cartesian storage layout: 32 cells per brick (one
-// 128-byte line of FP32 densities): runs of up to 16 cells along x (the
-// grid's fastest axis), the remaining doublings on the axis whose brick is
-// physically shortest, never beyond the grid's own extent (rounded up to a
-// power of two).  Returns log2 sizes in bs and bricks per axis in nb.
-inline void choose_bricks(const double cs[3], const int n[3], int bs[3], int nb[3], long long &n_store)
+// 128-byte line of FP32 densities); within a brick each axis's cell bits are
+// contiguous, in = sum_a (c_a mod 2^bs_a) << sh_a.  The first 8 cells of a
+// brick are one 64-byte line of the FP64 table, and the transport kernel
+// issues a ray's consecutive deposits together, so the line is made as close
+// to a physical cube as possible: its 3 bits go one at a time to the axis of
+// smallest physical extent cs_a 2^bs_a (ties: the lower axis); the other 2
+// bits go to the axis of smallest extent after that, which is placed last in
+// the index so the line stays the first 8 cells.  No axis gets more bits than
+// its own extent needs (rounded up to a power of two) unless the whole grid
+// is smaller than a brick (then x is padded).
+inline void choose_bricks(const double cs[3], const int n[3], int bs[3], int sh[3], int nb[3], long long &n_store)
 {
     int lim[3];
     for (int a = 0; a < 3; ++a) {
         bs[a] = 0;
+        sh[a] = 0;
         lim[a] = 0;
         while ((1 << lim[a]) < n[a]) lim[a]++;
     }
-    bs[0] = lim[0] < 4 ? lim[0] : 4;
-    for (int k = bs[0]; k < 5; ++k) {
+    auto pick = [&]() {
         int best = -1;
         double ext = 0.0;
-        for (int a = 1; a < 3; ++a) {
+        for (int a = 0; a < 3; ++a) {
             double e = cs[a] * (double)(1 << bs[a]);
             if (bs[a] < lim[a] && (best < 0 || e < ext)) {
                 best = a;
                 ext = e;
             }
         }
-        if (best < 0) best = 0; // grid smaller than a brick: pad along x
-        bs[best]++;
-    }
+        return best < 0 ? 0 : best; // grid smaller than a brick: pad along x
+    };
+    for (int k = 0; k < 3; ++k) bs[pick()]++;
+    const int last = pick();
+    for (int k = 0; k < 2; ++k) bs[last]++;
+    int pos = 0;
+    for (int a = 0; a < 3; ++a)
+        if (a != last) {
+            sh[a] = pos;
+            pos += bs[a];
+        }
+    sh[last] = pos;
     n_store = 32;
     for (int a = 0; a < 3; ++a) {
         nb[a] = (n[a] + (1 << bs[a]) - 1) >> bs[a];
@@ -196,11 +211,19 @@ inline void choose_bricks(const double cs[3], const int n[3], int bs[3], int nb[
     }
 }
 
-inline long long store_index_host(const int bs[3], const int nb[3], int ix, int iy, int iz)
+// Shifts of an explicitly requested brick shape: x fastest, then y, then z.
+inline void default_shifts(const int bs[3], int sh[3])
+{
+    sh[0] = 0;
+    sh[1] = bs[0];
+    sh[2] = bs[0] + bs[1];
+}
+
+inline long long store_index_host(const int bs[3], const int sh[3], const int nb[3], int ix, int iy, int iz)
 {
     long long brick = (ix >> bs[0]) + (long long)nb[0] * ((iy >> bs[1]) + (long long)nb[1] * (iz >> bs[2]));
-    int in = (ix & ((1 << bs[0]) - 1)) + ((iy & ((1 << bs[1]) - 1)) << bs[0]) +
-             ((iz & ((1 << bs[2]) - 1)) << (bs[0] + bs[1]));
+    int in = ((ix & ((1 << bs[0]) - 1)) << sh[0]) + ((iy & ((1 << bs[1]) - 1)) << sh[1]) +
+             ((iz & ((1 << bs[2]) - 1)) << sh[2]);
     return brick * 32 + in;
 }
 

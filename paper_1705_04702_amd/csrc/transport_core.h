@@ -131,7 +131,7 @@ template <typename Real, typename ImgT, int G> struct View {
     long long n_cells;
     // Cartesian storage layout: bricks of 2^bs[0] x 2^bs[1] x 2^bs[2] = 32 cells,
     // nb[] bricks per axis; n_store = cells per wavelength slice incl. padding
-    int bs[3], nb[3];
+    int bs[3], nb[3], sh[3]; // in-brick index: sum_a (c_a mod 2^bs_a) << sh_a
     long long n_store;
     // per wavelength
     int n_lambda;
@@ -221,8 +221,8 @@ template <typename Real, typename ImgT, int G>
 MCRT_HD int store_index(const View<Real, ImgT, G> &v, int ix, int iy, int iz)
 {
     int brick = (ix >> v.bs[0]) + v.nb[0] * ((iy >> v.bs[1]) + v.nb[1] * (iz >> v.bs[2]));
-    int in = (ix & ((1 << v.bs[0]) - 1)) + ((iy & ((1 << v.bs[1]) - 1)) << v.bs[0]) +
-             ((iz & ((1 << v.bs[2]) - 1)) << (v.bs[0] + v.bs[1]));
+    int in = ((ix & ((1 << v.bs[0]) - 1)) << v.sh[0]) + ((iy & ((1 << v.bs[1]) - 1)) << v.sh[1]) +
+             ((iz & ((1 << v.bs[2]) - 1)) << v.sh[2]);
     return brick * 32 + in;
 }
 

@@ -141,12 +141,22 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     v.n_ins = s->n_ins;
     std::vector<InsDesc<Real>> ins((size_t)(s->n_ins > 0 ? s->n_ins : 1));
     std::vector<double> inv4pid2((size_t)(s->n_ins > 0 ? s->n_ins : 1));
+    std::vector<std::vector<Real>> cols((size_t)(s->n_ins > 0 ? s->n_ins : 1));
     long long off = 0;
     for (int j = 0; j < s->n_ins; ++j) {
         const double *gm = s->ins_geom + 5 * j;
         HostInstrument h{gm[0], gm[1], gm[2], {gm[3], gm[4]}, {s->ins_npix[2 * j], s->ins_npix[2 * j + 1]}};
         make_ins_desc<Real>(h, off, ins[j], inv4pid2[j]);
         off += (long long)s->n_lambda * h.npix[0] * h.npix[1];
+        const int code = G == kCartesian ? axis_code(h) : -1;
+        if (code >= 0) {
+            std::vector<double> S;
+            int n3[3] = {s->n[0], s->n[1], s->n[2]};
+            column_map(s->density, n3, s->box, code, v.bs, v.sh, v.nb, v.n_store, S);
+            cols[j].assign(S.begin(), S.end());
+            ins[j].col = cols[j].data();
+            ins[j].col_axis = code;
+        }
     }
     v.ins = ins.data();
     std::vector<double> table((size_t)v.n_store * s->n_lambda, 0.0);

@@ -129,6 +129,7 @@ struct mcrt_sim {
     int *d_top = nullptr;
     void *d_optics = nullptr; // Optics<Real>[n_lambda], rewritten per run
     void *d_ins = nullptr;    // InsDesc<Real>[n_ins]
+    void *d_col[kMaxIns] = {}; // column maps of axis-aligned instruments (Cartesian), Real[n_store]
     std::atomic<int> busy{0};
     // learned proposal
     mcrt_proposal *prop = nullptr;
@@ -373,6 +374,10 @@ static void sim_free_device(mcrt_sim *s)
     dev_free(s->d_top);
     dev_free(s->d_optics);
     dev_free(s->d_ins);
+    for (int j = 0; j < kMaxIns; ++j) {
+        dev_free(s->d_col[j]);
+        s->d_col[j] = nullptr;
+    }
     s->d_density = nullptr;
     s->d_node = nullptr;
     s->d_top = nullptr;
@@ -391,7 +396,20 @@ void mcrt_sim_destroy(mcrt_sim *sim)
 template <typename Real> static int upload_instruments(mcrt_sim *s)
 {
     std::vector<InsDesc<Real>> d((size_t)std::max(s->n_ins, 1));
-    for (int j = 0; j < s->n_ins; ++j) make_ins_desc<Real>(s->ins[j], s->ins_offset[j], d[j], s->inv4pid2[j]);
+    const mcrt_grid *g = s->medium->grid;
+    for (int j = 0; j < s->n_ins; ++j) {
+        make_ins_desc<Real>(s->ins[j], s->ins_offset[j], d[j], s->inv4pid2[j]);
+        const int code = g->type == kCartesian ? axis_code(s->ins[j]) : -1;
+        if (code < 0) continue;
+        std::vector<double> S;
+        column_map(s->medium->density.data(), g->n, g->box, code, s->bs, s->sh, s->nb, s->n_store, S);
+        std::vector<Real> Sr(S.begin(), S.end());
+        int rc = dev_alloc(&s->d_col[j], Sr.size() * sizeof(Real));
+        if (rc) return rc;
+        HIP_TRY(hipMemcpy(s->d_col[j], Sr.data(), Sr.size() * sizeof(Real), hipMemcpyHostToDevice));
+        d[j].col = (const Real *)s->d_col[j];
+        d[j].col_axis = code;
+    }
     int rc = dev_alloc(&s->d_ins, d.size() * sizeof(InsDesc<Real>));
     if (rc) return rc;
     HIP_TRY(hipMemcpy(s->d_ins, d.data(), d.size() * sizeof(InsDesc<Real>), hipMemcpyHostToDevice));

@@ -41,6 +41,28 @@ inline void make_ins_desc(const HostInstrument &h, long long offset, InsDesc<Rea
     o.offset = offset;
     inv4pid2 = 1.0 / (4.0 * pi * h.distance * h.distance);
     o.inv4pid2 = (Real)inv4pid2;
+    o.col = nullptr;
+    o.col_axis = -1;
+}
+
+// Line of sight along a grid axis: one component exactly +-1, the others
+// below 1e-12 (cos 90 deg evaluates to 6e-17).  Returns 2 axis + (k < 0), or
+// -1.  A ray that drifts by less than 1e-12 of its length off the axis
+// crosses no other plane inside the grid (unless it starts within that
+// distance of one).
+inline int axis_code(const HostInstrument &h)
+{
+    const double pi = 3.14159265358979323846;
+    double i = h.incl_deg * pi / 180.0, a = h.azim_deg * pi / 180.0;
+    double k[3] = {std::sin(i) * std::cos(a), std::sin(i) * std::sin(a), std::cos(i)};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (std::fabs(k[ax]) != 1.0) continue;
+        bool ok = true;
+        for (int b = 0; b < 3; ++b)
+            if (b != ax && std::fabs(k[b]) > 1e-12) ok = false;
+        if (ok) return 2 * ax + (k[ax] < 0.0 ? 1 : 0);
+    }
+    return -1;
 }
 
 // Parameters of the proposal network as the FP64 scalar network reads them:
@@ -225,6 +247,35 @@ inline long long store_index_host(const int bs[3], const int sh[3], const int nb
     int in = ((ix & ((1 << bs[0]) - 1)) << sh[0]) + ((iy & ((1 << bs[1]) - 1)) << sh[1]) +
              ((iz & ((1 << bs[2]) - 1)) << sh[2]);
     return brick * 32 + in;
+}
+
+// Column map of a line of sight along +-axis (code = 2 axis + (k < 0)): for
+// every cell, the sum of density x cell width over the cells beyond it in the
+// direction of sight, up to the grid boundary (FP64, storage order; planes at
+// lo + j (hi - lo) / n).  The optical depth from a point in cell c to the
+// boundary is then kappa (rho_c d + S_c), d the distance to c's exit face.
+inline void column_map(const float *density, const int n[3], const double box[6], int code, const int bs[3],
+                       const int sh[3], const int nb[3], long long n_store, std::vector<double> &S)
+{
+    const int a = code >> 1;
+    const bool neg = (code & 1) != 0;
+    const int u = (a + 1) % 3, w = (a + 2) % 3;
+    const double cs = (box[3 + a] - box[a]) / (double)n[a];
+    S.assign((size_t)n_store, 0.0);
+    for (int iw = 0; iw < n[w]; ++iw)
+        for (int iu = 0; iu < n[u]; ++iu) {
+            double acc = 0.0;
+            for (int s = 0; s < n[a]; ++s) {
+                const int ia = neg ? s : n[a] - 1 - s; // from the far end of the line of sight
+                int c[3];
+                c[a] = ia;
+                c[u] = iu;
+                c[w] = iw;
+                S[(size_t)store_index_host(bs, sh, nb, c[0], c[1], c[2])] = acc;
+                const double lo = box[a] + (double)ia * cs, hi = box[a] + (double)(ia + 1) * cs;
+                acc = acc + (double)density[c[0] + (size_t)n[0] * (c[1] + (size_t)n[1] * c[2])] * (hi - lo);
+            }
+        }
 }
 
 } // namespace mcrt

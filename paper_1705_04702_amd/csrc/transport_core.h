@@ -113,6 +113,12 @@ template <typename Real> struct InsDesc {
     int nx, ny;
     long long offset; // first image element of this instrument
     Real inv4pid2;    // flux per unit of image accumulation
+    // Cartesian grids, line of sight along a grid axis: col[store(c)] = sum of
+    // density x path length over the cells beyond c up to the boundary, so a
+    // peel-off's optical depth needs no march; col_axis = 2 axis + (k < 0),
+    // -1 (col == nullptr) otherwise
+    const Real *col;
+    int col_axis;
 };
 
 template <typename Real> struct Optics {
@@ -613,6 +619,17 @@ MCRT_HD Stream stream_of(const View<Real, ImgT, G> &v, const Lane<Real> &ln)
     return Stream{v.key0, v.key1, ln.id, ln.lam, v.model};
 }
 
+// Optical depth to the boundary along axis A from the lane's march start:
+// the start cell from the start point to its exit face, then the column
+// beyond it (Cartesian grids).
+template <int A, typename Real, typename ImgT, int G>
+MCRT_HD Real column_tau(const View<Real, ImgT, G> &v, const Lane<Real> &ln, const Real *col)
+{
+    const Real tn = A == 0 ? ln.tn0 : (A == 1 ? ln.tn1 : ln.tn2);
+    const int cell = store_index(v, ln.c0, ln.c1, ln.c2);
+    return ln.opt.kappa * ((Real)v.density[cell] * (tn - ln.t) + col[cell]);
+}
+
 template <typename Real, typename ImgT, int G>
 MCRT_HD void begin_peel(const View<Real, ImgT, G> &v, Lane<Real> &ln, int j, bool emission)
 {
@@ -630,6 +647,23 @@ MCRT_HD void begin_peel(const View<Real, ImgT, G> &v, Lane<Real> &ln, int j, boo
     }
     ln.wpeel = w;
     begin_march(v, ln, in.kobs);
+    if constexpr (G == kCartesian) {
+        if (in.col != nullptr && ln.marching) {
+            // optical depth to the boundary along the axis: this cell from the
+            // start point to its exit face, then the column beyond it
+            // per-axis copies with compile-time axis numbers: a runtime choice
+            // among the lane's per-axis fields would move the lane to scratch
+            const int a = in.col_axis >> 1;
+            Real tau;
+            if (a == 0) tau = column_tau<0>(v, ln, in.col);
+            else if (a == 1) tau = column_tau<1>(v, ln, in.col);
+            else tau = column_tau<2>(v, ln, in.col);
+            ln.tau = tau;
+            ln.dropped = tau >= v.tau_peel_max;
+            ln.nseg = 1;
+            ln.marching = false;
+        }
+    }
 }
 
 template <typename Real, typename ImgT, int G>

@@ -186,10 +186,12 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     }
     __syncthreads();
 
-    // Segments per march iteration: FP32 Cartesian 8 (4 with the learned
-    // proposal, whose network needs the registers), octree 2; FP32 deposits
-    // are issued transposed through LDS, one slot per segment.
-    constexpr int kK = sizeof(Real) == 4 && G == kCartesian ? (LEARN ? 4 : 8) : BatchOf<G>::value;
+    // Segments per march iteration: FP32 Cartesian 8, FP32 octree 4 (4 and 2
+    // with the learned proposal, whose network needs the registers), FP64 as
+    // the host simulator; FP32 deposits are issued transposed through LDS,
+    // one slot per segment.
+    constexpr int kK = sizeof(Real) != 4 ? BatchOf<G>::value
+                                         : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 2 : 4));
     constexpr int kTR = sizeof(Real) == 4 ? kK : 0;
     __shared__ double *s_dp[kTR ? kBlock * kTR : 1];
     __shared__ double s_dv[kTR ? kBlock * kTR : 1];

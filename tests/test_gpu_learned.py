@@ -162,7 +162,7 @@ def test_histories_fp64_match_oracle(ctx, name):
     with np.errstate(divide="ignore", invalid="ignore"):
         Cr = np.where(Lr > 0, (ht[:, None] - hr[:, :, 13]) / np.where(Lr > 0, Lr, 1.0), 0.0).astype(np.float32)
     keep = Cr > 0
-    np.testing.assert_array_equal(C, Cr[keep])
+    np.testing.assert_allclose(C, Cr[keep], rtol=1e-6, atol=0)  # flux sums to rounding
     np.testing.assert_array_equal(X, hr[:, :, :9][keep].astype(np.float32))
     np.testing.assert_array_equal(KP, hr[:, :, 9:12][keep].astype(np.float32))
 

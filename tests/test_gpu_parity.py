@@ -299,3 +299,18 @@ def test_full_size_disk_in_the_bench_launch_configuration(ctx):
             r.close()
     finally:
         sim.close()
+
+
+def test_axis_aligned_instruments_fp64(ctx):
+    """Peel-offs along the six grid axes (column maps, no march) next to an
+    oblique one, on flat cells with sources inside and outside the grid and
+    peel-offs dropped at tau_peel_max: FP64 parity per pixel."""
+    sc = scenes.disk((20, 16, 10), 3, 20, tau_v_faceon=4.0)
+    sc.instruments = [scenes.Instrument(i, a, 1.0e4, (40.0, 40.0), (20, 20))
+                      for i, a in [(0, 0), (180, 0), (90, 0), (90, 180), (90, 90), (90, 270), (60, 30)]]
+    sc.tau_peel_max = 1.0
+    N = 600
+    o = oracle.run(sc, N, seed=13)
+    assert o["stats"]["peel_dropped"] > 0
+    g = gpu_run(ctx, sc, N, seed=13)
+    assert_fp64_parity(g, o)

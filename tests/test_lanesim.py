@@ -14,6 +14,12 @@ import lanesim
 import oracle
 from paper_1705_04702_amd import scenes
 
+def _axis_aligned(ins):
+    i, a = np.radians(ins.incl_deg), np.radians(ins.azim_deg)
+    k = np.array([np.sin(i) * np.cos(a), np.sin(i) * np.sin(a), np.cos(i)])
+    return any(abs(k[ax]) == 1.0 and all(abs(k[b]) <= 1e-12 for b in range(3) if b != ax) for ax in range(3))
+
+
 SCENES = {
     "sphere": (lambda: scenes.sphere(), 1500),
     "sphere_thick": (lambda: scenes.sphere(n=16, tau=8.0, albedo=0.95, g=-0.4), 300),
@@ -36,7 +42,8 @@ def test_lane_logic_matches_oracle_fp64(name):
         assert np.array_equal(a == 0, b == 0)
     for k in ("packets", "events", "prop_cells", "peel_adds", "peel_dropped", "capped"):
         assert l["stats"][k] == o["stats"][k], k
-    if o["stats"]["peel_dropped"] == 0:
+    if o["stats"]["peel_dropped"] == 0 and not any(_axis_aligned(i) for i in sc.instruments):
+        # peel-offs along a grid axis read a column map instead of marching
         assert l["stats"]["peel_cells"] == o["stats"]["peel_cells"]
     assert l["stats"]["guard"] == 0
 
@@ -130,8 +137,11 @@ def test_histories_match_oracle(name):
     E = 10
     o = oracle.run(sc, N, seed=5, histories=E, first_id=7, count=N - 20)
     l = lanesim.run(sc, N, seed=5, precision=1, histories=E, first_id=7, count=N - 20)
-    np.testing.assert_array_equal(l["hist"], o["hist"])
-    np.testing.assert_array_equal(l["hist_total"], o["hist_total"])
+    # features, directions and luminosities bit for bit; the flux columns to
+    # rounding (peel-offs along a grid axis sum the column in another order)
+    np.testing.assert_array_equal(l["hist"][:, :, :13], o["hist"][:, :, :13])
+    np.testing.assert_allclose(l["hist"][:, :, 13], o["hist"][:, :, 13], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(l["hist_total"], o["hist_total"], rtol=1e-12, atol=0)
     np.testing.assert_array_equal(l["table"], o["table"])
 
 
@@ -144,3 +154,26 @@ def test_learned_event_cap_matches_oracle():
     np.testing.assert_array_equal(l["table"], o["table"])
     np.testing.assert_array_equal(l["energy"], o["energy"])
     assert l["stats"]["capped"] == o["stats"]["capped"] == 600
+
+
+@pytest.mark.parametrize("incl,azim", [(0.0, 0.0), (180.0, 0.0), (90.0, 0.0), (90.0, 180.0), (90.0, 90.0),
+                                       (90.0, 270.0), (60.0, 0.0)])
+def test_axis_aligned_peel_offs_match_the_march(incl, azim):
+    """Peel-offs along a grid axis (column map: the optical depth of the rest
+    of the column from the start cell's exit face) give the oracle's images
+    to rounding, drops included, on a grid with flat cells, a source off the
+    grid's symmetry planes and sources outside the grid."""
+    sc = scenes.disk((12, 10, 6), 2, 24, tau_v_faceon=5.0)
+    sc.instruments = [scenes.Instrument(incl, azim, 1.0e4, (40.0, 40.0), (24, 24))]
+    sc.tau_peel_max = 0.5  # some peel-offs get dropped
+    o = oracle.run(sc, 300, seed=5)
+    l = lanesim.run(sc, 300, seed=5, precision=1)
+    np.testing.assert_array_equal(l["table"], o["table"])
+    for a, b in zip(l["images"], o["images"]):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+        assert np.array_equal(a == 0, b == 0)
+    for k in ("peel_adds", "peel_dropped", "events"):
+        assert l["stats"][k] == o["stats"][k], k
+    assert o["stats"]["peel_dropped"] > 0
+    if _axis_aligned(sc.instruments[0]):
+        assert l["stats"]["peel_cells"] == 0

@@ -33,9 +33,9 @@ using namespace mcrt;
 namespace {
 struct HostSink {
     static constexpr bool kLearn = true, kHist = true; // chosen at run time
-    void deposit(double *p, double v)
+    void deposit(double *table, long long slab, int cell, double v)
     {
-        if (v != 0.0) *p += v;
+        if (v != 0.0) table[slab + cell] += v;
     }
     template <typename L, typename T> void pixel(L &, T *images, long long idx, T v) { images[idx] += v; }
 };

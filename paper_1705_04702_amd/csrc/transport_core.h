@@ -474,7 +474,7 @@ MCRT_HD bool apply_segment(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &
     if (ln.mode == kProp) {
         Real x = -Math<Real>::e_expm1(-dtau);
         Real A = ln.wabs * ln.E * x;
-        sink.deposit(v.table + (long long)ln.lam * v.n_store + cell, (double)A);
+        sink.deposit(v.table, (long long)ln.lam * v.n_store, cell, (double)A);
         ty.absorbed += (double)A;
         ln.E = ln.E * (Real(1) - x);
         ln.tau = ln.tau + dtau;

@@ -28,44 +28,80 @@
 
 namespace mcrt {
 
-// TRK > 0: a march iteration's deposits (at most TRK per lane) go through a
-// per-wave LDS tile and are issued transposed -- one atomic instruction then
-// carries TRK consecutive cells of each of 64/TRK rays, so lanes whose cells
-// share a cache line of the table travel as one L2 request (the L2 retires
-// FP64 atomics per line request: ~1.8e11/s for 8 lanes on one line against
-// ~2.4e10/s for 64 scattered lanes).
-template <bool LEARN, bool HIST, int TRK = 0> struct DevSink {
+// TRK > 0 (FP32 kernels): deposits go through a per-wave LDS tile of TRK
+// slots per lane and are issued transposed -- one atomic instruction carries
+// the slots of 64/TRK rays, a ray's slots in consecutive lanes, so the cells
+// of one ray that share a line of the table travel as one L2 request (the L2
+// retires FP64 atomics per 64-byte line request: ~1.8e11/s for 8 lanes on one
+// line against ~2.4e10/s for 64 scattered lanes).  The deposits of a ray's
+// open run -- its latest cells that share one line -- are held back while
+// the propagation march goes on, so a run that spans two march iterations
+// still goes out as one request (at most TRK - K slots are held: K new
+// deposits per iteration always fit; TRK == K holds nothing).  A slot holds
+// the cell (u32) and the FP32 absorbed luminosity, which converts to FP64
+// exactly.
+template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
     static constexpr bool kLearn = LEARN, kHist = HIST;
-    double **dp = nullptr; // this lane's TRK slots (TRK > 0)
-    double *dv = nullptr;
-    int np = 0;
-    __device__ __forceinline__ void deposit(double *p, double v)
+    static constexpr int kPitch = 64 + (TRK > 0 ? 64 / TRK : 0); // slot-major rows, padded
+    static constexpr bool kHold = TRK > K;
+    static_assert(TRK == 0 || (64 % TRK == 0 && TRK >= K), "slot tile");
+    uint32_t *sc = nullptr; // this lane's column of the wave's slot tiles
+    float *sv = nullptr;
+    int np = 0;        // slots in use
+    int run = 0;       // first slot of the open run
+    uint32_t rl = ~0u; // table line of the open run
+    __device__ __forceinline__ void deposit(double *table, long long slab, int cell, double v)
     {
         if constexpr (TRK > 0) {
             if (v != 0.0) {
-                dp[np] = p;
-                dv[np] = v;
+                if constexpr (kHold) {
+                    const uint32_t line = (uint32_t)cell >> 3;
+                    if (line != rl) {
+                        rl = line;
+                        run = np;
+                    }
+                }
+                sc[np * kPitch] = (uint32_t)cell;
+                sv[np * kPitch] = (float)v;
                 ++np;
             }
         } else {
-            if (v != 0.0) unsafeAtomicAdd(p, v);
+            if (v != 0.0) unsafeAtomicAdd(table + slab + cell, v);
         }
     }
-    // Issues the iteration's deposits; whole wave active.
-    __device__ __forceinline__ void flush(int lane, double *const *wave_p, const double *wave_v)
+    // Issues the slots of closed runs; `hold` keeps the open run for the next
+    // iteration (the lane's propagation march goes on).  slab: this lane's
+    // wavelength slab of the table.  Whole wave active.
+    __device__ __forceinline__ void flush(int lane, bool hold, double *slab, const uint32_t *tile_c,
+                                          const float *tile_v, double **wave_slab, int *wave_lim)
     {
         if constexpr (TRK > 0) {
-            for (int k = np; k < TRK; ++k) dp[k] = nullptr;
-            np = 0;
-            wave_lds_sync();
             constexpr int R = 64 / TRK;
+            int keep = 0;
+            if constexpr (kHold) {
+                keep = hold ? np - run : 0;
+                keep = keep < TRK - K ? keep : TRK - K;
+            }
+            const int lim = np - keep;
+            wave_slab[lane] = slab;
+            wave_lim[lane] = lim;
+            wave_lds_sync();
+            const int s = lane % TRK;
 #pragma unroll
             for (int j = 0; j < TRK; ++j) {
-                const int slot = (R * j + lane / TRK) * TRK + lane % TRK;
-                double *p = wave_p[slot];
-                if (p) unsafeAtomicAdd(p, wave_v[slot]);
+                const int ray = R * j + lane / TRK;
+                if (s < wave_lim[ray])
+                    unsafeAtomicAdd(wave_slab[ray] + tile_c[s * kPitch + ray], (double)tile_v[s * kPitch + ray]);
             }
             wave_lds_sync();
+            if constexpr (kHold) {
+                for (int i = 0; i < keep; ++i) {
+                    sc[i * kPitch] = sc[(lim + i) * kPitch];
+                    sv[i * kPitch] = sv[(lim + i) * kPitch];
+                }
+                run = 0;
+            }
+            np = keep;
         }
     }
     // Pixel adds are held in the lane (one pending add) and combined across
@@ -188,20 +224,27 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
 
     // Segments per march iteration: FP32 Cartesian 8, FP32 octree 4 (4 and 2
     // with the learned proposal, whose network needs the registers), FP64 as
-    // the host simulator; FP32 deposits are issued transposed through LDS,
-    // one slot per segment.
+    // the host simulator.  FP32 deposits are issued transposed through LDS:
+    // Cartesian runs hold their open run (16 slots per lane); octree runs and
+    // the learned proposal (registers, LDS) take one slot per segment -- on
+    // the octree's smaller tables the extra issue costs more than the held
+    // runs save.
     constexpr int kK = sizeof(Real) != 4 ? BatchOf<G>::value
                                          : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 2 : 4));
-    constexpr int kTR = sizeof(Real) == 4 ? kK : 0;
-    __shared__ double *s_dp[kTR ? kBlock * kTR : 1];
-    __shared__ double s_dv[kTR ? kBlock * kTR : 1];
-    DevSink<LEARN, HIST, kTR> sink;
-    if constexpr (kTR > 0) {
-        sink.dp = s_dp + threadIdx.x * kTR;
-        sink.dv = s_dv + threadIdx.x * kTR;
-    }
+    constexpr int kTR = sizeof(Real) == 4 ? (G == kCartesian && !LEARN ? 16 : kK) : 0;
+    typedef DevSink<LEARN, HIST, kTR, kK> SinkT;
+    constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
+    __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
+    __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
+    __shared__ double *s_slab[kTR ? kBlock : 1];
+    __shared__ int s_lim[kTR ? kBlock : 1];
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
+    SinkT sink;
+    if constexpr (kTR > 0) {
+        sink.sc = s_tc + wave * kTile + lane;
+        sink.sv = s_tv + wave * kTile + lane;
+    }
     Lane<Real> ln;
     ln.mode = kDead;
     ln.marching = false;
@@ -267,7 +310,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
         // march: every marching lane advances one cell per iteration
         for (;;) {
             if (ln.marching) march_batch<kK>(v, ln, ty, sink);
-            sink.flush(lane, s_dp + wave * 64 * kTR, s_dv + wave * 64 * kTR);
+            sink.flush(lane, ln.marching && ln.mode == kProp, v.table + (long long)ln.lam * v.n_store,
+                       s_tc + wave * kTile, s_tv + wave * kTile, s_slab + wave * 64, s_lim + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;
@@ -338,17 +382,23 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
 template <typename Real, typename ImgT>
 __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real, ImgT> a)
 {
+    // one deposit slot per segment: the batch's small tables stay in the L2,
+    // where holding runs does not pay for its extra issue
     constexpr int kK = sizeof(Real) == 4 ? 8 : BatchOf<0>::value;
     constexpr int kTR = sizeof(Real) == 4 ? kK : 0;
-    __shared__ double *s_dp[kTR ? kBlock * kTR : 1];
-    __shared__ double s_dv[kTR ? kBlock * kTR : 1];
-    DevSink<false, false, kTR> sink;
-    if constexpr (kTR > 0) {
-        sink.dp = s_dp + threadIdx.x * kTR;
-        sink.dv = s_dv + threadIdx.x * kTR;
-    }
+    typedef DevSink<false, false, kTR, kK> SinkT;
+    constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
+    __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
+    __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
+    __shared__ double *s_slab[kTR ? kBlock : 1];
+    __shared__ int s_lim[kTR ? kBlock : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = __lane_id();
+    SinkT sink;
+    if constexpr (kTR > 0) {
+        sink.sc = s_tc + wave * kTile + lane;
+        sink.sv = s_tv + wave * kTile + lane;
+    }
     Lane<Real> ln;
     ln.mode = kDead;
     ln.marching = false;
@@ -423,7 +473,8 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
         }
         for (;;) {
             if (ln.marching) march_batch<kK>(V(), ln, ty, sink);
-            sink.flush(lane, s_dp + wave * 64 * kTR, s_dv + wave * 64 * kTR);
+            sink.flush(lane, ln.marching && ln.mode == kProp, V().table + (long long)ln.lam * V().n_store,
+                       s_tc + wave * kTile, s_tv + wave * kTile, s_slab + wave * 64, s_lim + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;

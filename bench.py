@@ -236,6 +236,43 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_curve(args, scene, workload, N):
+    """Throughput against the packets of one launch (1e4 .. the full run): the
+    fixed launch and tail costs amortised over more packets.  Each point is
+    the median of 3 launches after one warm-up launch of the same size."""
+    import torch
+    from paper_1705_04702_amd import mcrt
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, scene, mcrt.FP32)
+    nl = scene.n_lambda
+    full = N * nl
+    totals = [t for t in (10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7, 10 ** 8) if t < full] + [full]
+    rows = []
+    for tot in totals:
+        cnt = max(1, tot // nl)
+        res = sim.new_result()
+        walls, kms = [], []
+        for k in range(4):
+            res.zero()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sim.run_into(res, N, seed=0, first_id=0, count=cnt)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t
+            if k:
+                walls.append(w)
+                kms.append(res.stats()["kernel_ms"])
+        res.close()
+        wall, km = sorted(walls)[1], sorted(kms)[1]
+        rows.append({"packets": cnt * nl, "kernel_ms": km, "wall_ms": wall * 1e3,
+                     "packets_per_s_kernel": cnt * nl / (km / 1e3),
+                     "packets_per_s_wall": cnt * nl / wall})
+        print(f"[curve] {cnt * nl} packets: kernel {km:.3f} ms, wall {wall * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    sim.close()
+    print(json.dumps({"metric": "packets/s against packets per launch", "workload": workload,
+                      "unit": "packets/s", "dtype": "f32", "points": rows}), flush=True)
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle, one wavelength per task, tasks spread over
 # processes (replicated scene, per-process tables summed -- the paper's task
@@ -260,6 +297,7 @@ def _oracle_task(args):
 
 def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
     global _SC
+    import numpy as np
     import oracle
     oracle.lib()
     _SC = scene
@@ -268,7 +306,13 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
     t0 = time.perf_counter()
     _oracle_task((scene.n_lambda // 2, n_per_lambda, 50, 0))
     per_packet = (time.perf_counter() - t0) / 50.0
-    count = max(20, int(seconds_target * cores / max(per_packet, 1e-7) / scene.n_lambda))
+    count = min(n_per_lambda, max(20, int(seconds_target * cores / max(per_packet, 1e-7) / scene.n_lambda)))
+    # one core: the same ids over 8 wavelengths spread across the grid, serially
+    c1 = min(n_per_lambda, max(10, int(seconds_target / 4 / max(per_packet, 1e-7) / 8)))
+    lams = sorted({int(round(x)) for x in np.linspace(0, scene.n_lambda - 1, 8)})
+    t = time.perf_counter()
+    p1 = sum(_oracle_task((ell, n_per_lambda, c1, 0))[0] for ell in lams)
+    single = p1 / (time.perf_counter() - t)
     tasks = [(ell, n_per_lambda, count, 0) for ell in range(scene.n_lambda)]
     ctx = mp.get_context("fork")
     t = time.perf_counter()
@@ -279,7 +323,9 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
     return {"value": packets / wall, "unit": "packets/s", "cores": cores, "kind": "oracle",
             "sample": f"packet ids [0, {count}) of each of the {scene.n_lambda} wavelengths "
                       f"({packets} packets, {wall:.1f} s wall), one wavelength per task on "
-                      f"{cores} processes"}
+                      f"{cores} processes",
+            "single_core": {"value": single, "unit": "packets/s",
+                            "sample": f"packet ids [0, {c1}) of wavelengths {lams}, one process"}}
 
 
 def microbenchmarks():
@@ -312,6 +358,8 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--threshold", type=int, default=0)
     ap.add_argument("--brick", default="", help="log2 brick sizes, e.g. 1,0,4")
+    ap.add_argument("--curve", action="store_true",
+                    help="packets/s against packets per launch, 1e4 up to the full workload (one JSON line)")
     ap.add_argument("--microbench", action="store_true",
                     help="only print the memory-system microbenchmarks (one JSON line)")
     ap.add_argument("--hist-packets", type=int, default=10_000_000, help="torus-learned: history packets")
@@ -354,6 +402,9 @@ def main():
         return
     scene, workload = make_scene(args.workload)
     N = args.n_per_lambda or WORKLOADS[args.workload][0]
+    if args.curve:
+        bench_curve(args, scene, workload, N)
+        return
     B = min(args.step_packets, N)
     ctx = mcrt.Context(0)
     brick = tuple(int(x) for x in args.brick.split(",")) if args.brick else None

@@ -44,25 +44,28 @@ template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
     static constexpr bool kLearn = LEARN, kHist = HIST;
     static constexpr int kPitch = 64 + (TRK > 0 ? 64 / TRK : 0); // slot-major rows, padded
     static constexpr bool kHold = TRK > K;
-    static_assert(TRK == 0 || (64 % TRK == 0 && TRK >= K), "slot tile");
+    static_assert(TRK == 0 || (64 % TRK == 0 && TRK <= 16 && TRK >= K), "slot tile");
     uint32_t *sc = nullptr; // this lane's column of the wave's slot tiles
     float *sv = nullptr;
     int np = 0;        // slots in use
-    int run = 0;       // first slot of the open run
+    int base = 0;      // ring position of the first slot in use (kHold)
+    int run = 0;       // first slot (from base) of the open run
     uint32_t rl = ~0u; // table line of the open run
     __device__ __forceinline__ void deposit(double *table, long long slab, int cell, double v)
     {
         if constexpr (TRK > 0) {
             if (v != 0.0) {
+                int slot = np;
                 if constexpr (kHold) {
                     const uint32_t line = (uint32_t)cell >> 3;
                     if (line != rl) {
                         rl = line;
                         run = np;
                     }
+                    slot = (base + np) & (TRK - 1);
                 }
-                sc[np * kPitch] = (uint32_t)cell;
-                sv[np * kPitch] = (float)v;
+                sc[slot * kPitch] = (uint32_t)cell;
+                sv[slot * kPitch] = (float)v;
                 ++np;
             }
         } else {
@@ -70,10 +73,13 @@ template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
         }
     }
     // Issues the slots of closed runs; `hold` keeps the open run for the next
-    // iteration (the lane's propagation march goes on).  slab: this lane's
-    // wavelength slab of the table.  Whole wave active.
-    __device__ __forceinline__ void flush(int lane, bool hold, double *slab, const uint32_t *tile_c,
-                                          const float *tile_v, double **wave_slab, int *wave_lim)
+    // iteration (the lane's propagation march goes on).  Every lane posts one
+    // word for its ray (wavelength, ring base, slots to issue), laid out so
+    // that an issuing lane reads the words of all its rays with 128-bit loads;
+    // the slots are read four rays at a time, so a flush waits on a few LDS
+    // round trips.  table: the wave's table (uniform).  Whole wave active.
+    __device__ __forceinline__ void flush(int lane, bool hold, int lam, double *table, long long n_store,
+                                          const uint32_t *tile_c, const float *tile_v, uint32_t *wave_word)
     {
         if constexpr (TRK > 0) {
             constexpr int R = 64 / TRK;
@@ -83,22 +89,45 @@ template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
                 keep = keep < TRK - K ? keep : TRK - K;
             }
             const int lim = np - keep;
-            wave_slab[lane] = slab;
-            wave_lim[lane] = lim;
+            // lam < 2^20 (the medium's limit), base < 16, lim <= 16
+            wave_word[(lane % R) * TRK + lane / R] = ((uint32_t)lam << 9) | ((uint32_t)base << 5) | (uint32_t)lim;
             wave_lds_sync();
-            const int s = lane % TRK;
+            const int s = lane % TRK, q = lane / TRK;
+            constexpr int GW = TRK < 4 ? TRK : 4; // rays per group
 #pragma unroll
-            for (int j = 0; j < TRK; ++j) {
-                const int ray = R * j + lane / TRK;
-                if (s < wave_lim[ray])
-                    unsafeAtomicAdd(wave_slab[ray] + tile_c[s * kPitch + ray], (double)tile_v[s * kPitch + ray]);
+            for (int g = 0; g < TRK / GW; ++g) {
+                uint32_t w[GW];
+                if constexpr (GW == 4) {
+                    const uint4 x = reinterpret_cast<const uint4 *>(wave_word + q * TRK)[g];
+                    w[0] = x.x;
+                    w[1] = x.y;
+                    w[2] = x.z;
+                    w[3] = x.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < GW; ++i) w[i] = wave_word[q * TRK + GW * g + i];
+                }
+                uint32_t c[GW];
+                float a[GW];
+#pragma unroll
+                for (int i = 0; i < GW; ++i) {
+                    const int ray = R * (GW * g + i) + q;
+                    const int slot = kHold ? (int)((((w[i] >> 5) & 15u) + (uint32_t)s) & (TRK - 1)) : s;
+                    c[i] = tile_c[slot * kPitch + ray];
+                    a[i] = tile_v[slot * kPitch + ray];
+                }
+#pragma unroll
+                for (int i = 0; i < GW; ++i) {
+                    if ((uint32_t)s < (w[i] & 31u)) {
+                        double *p = table + ((long long)(w[i] >> 9) * n_store + c[i]);
+                        __builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double *)p,
+                                                                (double)a[i]);
+                    }
+                }
             }
             wave_lds_sync();
             if constexpr (kHold) {
-                for (int i = 0; i < keep; ++i) {
-                    sc[i * kPitch] = sc[(lim + i) * kPitch];
-                    sv[i * kPitch] = sv[(lim + i) * kPitch];
-                }
+                base = (base + lim) & (TRK - 1);
                 run = 0;
             }
             np = keep;
@@ -236,8 +265,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
     __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
-    __shared__ double *s_slab[kTR ? kBlock : 1];
-    __shared__ int s_lim[kTR ? kBlock : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_word[kTR ? kBlock : 4];
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     SinkT sink;
@@ -310,8 +338,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
         // march: every marching lane advances one cell per iteration
         for (;;) {
             if (ln.marching) march_batch<kK>(v, ln, ty, sink);
-            sink.flush(lane, ln.marching && ln.mode == kProp, v.table + (long long)ln.lam * v.n_store,
-                       s_tc + wave * kTile, s_tv + wave * kTile, s_slab + wave * 64, s_lim + wave * 64);
+            sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, v.table, v.n_store, s_tc + wave * kTile,
+                       s_tv + wave * kTile, s_word + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;
@@ -390,8 +418,7 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
     __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
-    __shared__ double *s_slab[kTR ? kBlock : 1];
-    __shared__ int s_lim[kTR ? kBlock : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_word[kTR ? kBlock : 4];
     const int wave = threadIdx.x >> 6;
     const int lane = __lane_id();
     SinkT sink;
@@ -473,8 +500,8 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
         }
         for (;;) {
             if (ln.marching) march_batch<kK>(V(), ln, ty, sink);
-            sink.flush(lane, ln.marching && ln.mode == kProp, V().table + (long long)ln.lam * V().n_store,
-                       s_tc + wave * kTile, s_tv + wave * kTile, s_slab + wave * 64, s_lim + wave * 64);
+            sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, V().table, V().n_store,
+                       s_tc + wave * kTile, s_tv + wave * kTile, s_word + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             if (active == 0 || __popcll(waiting) >= a.threshold) break;

@@ -385,6 +385,25 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
         }
         te = rmax(tmin, ln.t);
         cell = store_index(v, ln.c0, ln.c1, ln.c2);
+        if constexpr (sizeof(Real) == 4) {
+            // FP32: branch-free -- the lanes of a wave step different axes.
+            // Each axis' next crossing is computed and kept only on the axis
+            // stepped (an axis with d = 0 is never stepped: its crossing
+            // stays at infinity).
+            const int u0 = ln.d[0] > Real(0) ? 1 : 0, u1 = ln.d[1] > Real(0) ? 1 : 0,
+                      u2 = ln.d[2] > Real(0) ? 1 : 0;
+            ln.c0 += am == 0 ? 2 * u0 - 1 : 0;
+            ln.c1 += am == 1 ? 2 * u1 - 1 : 0;
+            ln.c2 += am == 2 ? 2 * u2 - 1 : 0;
+            exits = (unsigned)ln.c0 >= (unsigned)v.n[0] || (unsigned)ln.c1 >= (unsigned)v.n[1] ||
+                    (unsigned)ln.c2 >= (unsigned)v.n[2];
+            const Real p0 = plane_t(v, ln, 0, ln.c0 + u0), p1 = plane_t(v, ln, 1, ln.c1 + u1),
+                       p2 = plane_t(v, ln, 2, ln.c2 + u2);
+            ln.tn0 = am == 0 ? p0 : ln.tn0;
+            ln.tn1 = am == 1 ? p1 : ln.tn1;
+            ln.tn2 = am == 2 ? p2 : ln.tn2;
+            return exits;
+        }
         // explicit per-axis branches (a loop over `a == am` gets folded into a
         // runtime-indexed store, which would move the arrays to scratch)
         if (am == 0) {
@@ -471,45 +490,39 @@ MCRT_HD bool apply_segment(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &
     ln.nseg++;
     const Real kr = ln.opt.kappa * (Real)rho;
     const Real dtau = kr * ds;
+    const Real tprev = ln.tau;
+    ln.tau = tprev + dtau;
     if (ln.mode == kProp) {
         Real x = -Math<Real>::e_expm1(-dtau);
         Real A = ln.wabs * ln.E * x;
         sink.deposit(v.table, (long long)ln.lam * v.n_store, cell, (double)A);
         ty.absorbed += (double)A;
         ln.E = ln.E * (Real(1) - x);
-        ln.tau = ln.tau + dtau;
         ty.prop_cells++;
         return false;
     }
-    if (ln.mode == kLocate) {
-        ty.locate_cells++;
-        Real tprev = ln.tau;
-        ln.tau = ln.tau + dtau;
-        if (dtau > Real(0)) {
-            ln.a_t0 = t_start;
-            ln.a_tau = tprev;
-            ln.a_kr = kr;
-            ln.a_ds = ds;
-            ln.rho_star = (Real)rho;
-        }
-        if (ln.tau >= ln.tau_int) {
-            ln.found = true;
-            return true;
-        }
-        return false;
-    }
-    ln.tau = ln.tau + dtau;
-    ty.peel_cells++;
-    if (ln.tau >= v.tau_peel_max) {
-        ln.dropped = true;
-        return true;
-    }
-    return false;
+    // interaction search and peel-off depth, written as selects: the lanes of
+    // a wave mix both
+    const bool loc = ln.mode == kLocate;
+    const bool save = loc && dtau > Real(0); // last segment with positive depth
+    ln.a_t0 = save ? t_start : ln.a_t0;
+    ln.a_tau = save ? tprev : ln.a_tau;
+    ln.a_kr = save ? kr : ln.a_kr;
+    ln.a_ds = save ? ds : ln.a_ds;
+    ln.rho_star = save ? (Real)rho : ln.rho_star;
+    ty.locate_cells += loc ? 1u : 0u;
+    ty.peel_cells += loc ? 0u : 1u;
+    const bool hit = ln.tau >= (loc ? ln.tau_int : v.tau_peel_max);
+    ln.found = ln.found || (hit && loc);
+    ln.dropped = ln.dropped || (hit && !loc);
+    return hit;
 }
 
 // K segments of the march: K geometric steps, then K independent density
 // loads in flight together, then the segments applied in order (the same
-// operations in the same order as one segment at a time).
+// operations in the same order as one segment at a time).  A Cartesian step
+// is pure arithmetic, so it also runs past the ray's exit (its results are
+// not used) rather than branching; every load reads a valid cell.
 template <int K, typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void march_batch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
@@ -523,17 +536,17 @@ MCRT_HD void march_batch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty
         cell[k] = 0;
         ts[k] = ln.t;
         ds[k] = Real(0);
-        if (more) {
+        if (G == kCartesian || more) {
             Real te;
             bool exits = geo_step(v, ln, ty, cell[k], te);
             ds[k] = te - ln.t;
             ln.t = te;
-            more = !exits;
+            more = more && !exits;
         }
     }
     float rho[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) rho[k] = ok[k] ? v.density[cell[k]] : 0.0f;
+    for (int k = 0; k < K; ++k) rho[k] = v.density[ok[k] ? cell[k] : 0];
     bool stop = false;
 #pragma unroll
     for (int k = 0; k < K; ++k)

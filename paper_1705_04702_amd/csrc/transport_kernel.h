@@ -408,7 +408,7 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
 // switches to a chunk of another model (tallies are flushed at the switch).
 // The model index is the fourth word of every packet's Philox counter.
 template <typename Real, typename ImgT>
-__global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real, ImgT> a)
+__device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a)
 {
     // one deposit slot per segment: the batch's small tables stay in the L2,
     // where holding runs does not pay for its extra issue
@@ -510,10 +510,27 @@ __global__ void __launch_bounds__(kBlock) batch_transport_kernel(BatchArgs<Real,
     if (cur_model >= 0) flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
 }
 
+// FP32: at most 168 VGPRs, three waves per SIMD, as the single-model kernels.
+template <typename ImgT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+batch_transport_kernel_f32(BatchArgs<float, ImgT> a)
+{
+    batch_body<float, ImgT>(a);
+}
+
+template <typename ImgT>
+__global__ void __launch_bounds__(kBlock) batch_transport_kernel_f64(BatchArgs<double, ImgT> a)
+{
+    batch_body<double, ImgT>(a);
+}
+
 template <typename Real, typename ImgT>
 hipError_t launch_batch_impl(const BatchArgs<Real, ImgT> &a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((batch_transport_kernel<Real, ImgT>), dim3(grid), dim3(kBlock), 0, stream, a);
+    if constexpr (sizeof(Real) == 4)
+        hipLaunchKernelGGL(batch_transport_kernel_f32<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(batch_transport_kernel_f64<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

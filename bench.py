@@ -358,6 +358,7 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--threshold", type=int, default=0)
     ap.add_argument("--brick", default="", help="log2 brick sizes, e.g. 1,0,4")
+    ap.add_argument("--top-level", type=int, default=-1, help="octree top-table level (-1: the library's)")
     ap.add_argument("--curve", action="store_true",
                     help="packets/s against packets per launch, 1e4 up to the full workload (one JSON line)")
     ap.add_argument("--microbench", action="store_true",
@@ -410,7 +411,7 @@ def main():
     brick = tuple(int(x) for x in args.brick.split(",")) if args.brick else None
     sim = mcrt.Sim(ctx, scene, mcrt.FP32, chunk=args.chunk or None,
                    waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None,
-                   brick=brick)
+                   brick=brick, top_level=args.top_level if args.top_level >= 0 else None)
     if args.autotune:
         t = mcrt.autotune([sim], [max(1, min(N, B) // 20)], seed=0,
                           cache_path=os.path.join(ROOT, "_build", "tune_cache.txt"))
@@ -451,18 +452,23 @@ def main():
 
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     achieved = bytes_alg / args.steps / avg_kernel_s / 1e9
-    traffic = None
+    traffic, req_per_packet = None, None
     prof = os.path.join(ROOT, "profiles", f"transport_{args.workload}_traffic.json")
     if os.path.exists(prof):
         meta = json.load(open(prof))
         if meta.get("kernel_hash") == kernel_sources_hash():
             traffic = meta["hbm_bytes_per_packet"] * packets / args.steps
-    # the atomic-throughput ceiling measured on this device (random FP64 atomic
-    # adds over a working set the size of one wavelength slice of the table)
+            req_per_packet = meta.get("atomic_requests_per_packet")
+    # The atomic ceiling measured on this device: random FP64 atomic adds over a
+    # working set the size of one wavelength slice of the table, one L2 atomic
+    # request each (the L2 forwards every atomic request to the memory side).
+    # The kernel's requests per packet come from the TCC_ATOMIC counter of the
+    # committed profile while the kernel sources are unchanged.
     slice_bytes = 8 * scene.n_cells
     atomic_ceiling = mcrt.microbench("atomic_f64", max(slice_bytes, 1 << 21), 1 << 28)
     n_atomic = st["prop_cells"] * packets / max(st["packets"], 1)
     atomics_per_s = n_atomic / args.steps / avg_kernel_s
+    req_per_s = req_per_packet * packets / args.steps / avg_kernel_s if req_per_packet else None
     out = {
         "metric": METRIC,
         "value": packets / T,
@@ -481,9 +487,10 @@ def main():
                    "instruments": [list(i.npix) for i in scene.instruments]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "atomic_roofline": {"achieved": atomics_per_s, "peak": atomic_ceiling, "unit": "FP64 atomics/s",
-                            "frac": atomics_per_s / atomic_ceiling,
-                            "peak_kind": "measured random FP64 atomic adds, device scope"},
+        "atomic_roofline": {"achieved": req_per_s, "peak": atomic_ceiling, "unit": "atomic requests/s",
+                            "frac": req_per_s / atomic_ceiling if req_per_s else None,
+                            "deposits_per_s": atomics_per_s,
+                            "peak_kind": "measured random FP64 atomic adds (one request each), device scope"},
         "energy_balance": balance,
         "counters_per_packet": {f: st[f] / max(st["packets"], 1) for f in
                                 ("events", "prop_cells", "locate_cells", "peel_cells", "peel_adds")},

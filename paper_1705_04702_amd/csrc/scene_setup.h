@@ -165,7 +165,10 @@ inline int encode_octree(int64_t n_nodes, const int32_t *first_child, int64_t n_
 }
 
 // Dense top table of the octree at level top_level: for each block the
-// deepest node at or above that level containing it, packed (level << 27) | node.
+// deepest node at or above that level containing it, stored as that node's
+// own entry so the walk starts one load further down: (level << 27) | first
+// child for an internal node, 1 << 31 | (level << 27) | cell for a leaf
+// (level <= 15; node and cell indices below 2^27).
 inline void build_top_table(const std::vector<int32_t> &node, int top_level, std::vector<int32_t> &top)
 {
     int T = 1 << top_level;
@@ -180,7 +183,10 @@ inline void build_top_table(const std::vector<int32_t> &node, int top_level, std
                     nd = node[(size_t)nd] + child;
                     level++;
                 }
-                top[((size_t)bz * T + by) * T + bx] = (level << 27) | nd;
+                const int32_t val = node[(size_t)nd];
+                const uint32_t e = val >= 0 ? ((uint32_t)level << 27) | (uint32_t)val
+                                            : (1u << 31) | ((uint32_t)level << 27) | (uint32_t)(-val - 1);
+                top[((size_t)bz * T + by) * T + bx] = (int32_t)e;
             }
 }
 

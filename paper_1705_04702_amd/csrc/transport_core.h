@@ -423,15 +423,14 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
         // locate the leaf holding lattice point ci: dense top table, then descend
         const int sh = v.depth - v.top_level;
         const int T = 1 << v.top_level;
-        int packed = v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
-        int level = packed >> 27;
-        int nd = packed & ((1 << 27) - 1);
-        int val = v.node[nd];
+        const uint32_t packed = (uint32_t)v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
+        int level = (int)((packed >> 27) & 15u);
+        const int pay = (int)(packed & ((1u << 27) - 1));
+        int val = (packed >> 31) ? -pay - 1 : pay; // the block's node entry
         while (val >= 0) {
             int bit = v.depth - 1 - level;
             int child = ((ln.c0 >> bit) & 1) + 2 * ((ln.c1 >> bit) & 1) + 4 * ((ln.c2 >> bit) & 1);
-            nd = val + child;
-            val = v.node[nd];
+            val = v.node[val + child];
             level++;
         }
         cell = -val - 1;

@@ -93,7 +93,10 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         depth = encode_octree(s->n_nodes, s->first_child, s->n_cells, node, err);
         if (depth < 0) return -2;
         v.top_level = s->top_level >= 0 ? (s->top_level < depth ? s->top_level : depth) : (depth < 7 ? depth : 7);
-        build_top_table(node, v.top_level, top);
+        std::vector<int32_t> blocks;
+        if (!build_walk(node, depth, v.top_level, top, blocks, err)) return -2;
+        node.swap(blocks);
+        if (node.empty()) node.assign(1, 0);
         for (int a = 0; a < 3; ++a) v.n[a] = 1 << depth;
     } else {
         for (int a = 0; a < 3; ++a) v.n[a] = s->n[a];

@@ -501,8 +501,11 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         int depth = encode_octree((int64_t)g->first_child.size(), g->first_child.data(), g->n_cells, node, err);
         s->depth = depth;
         s->top_level = o.top_level >= 0 ? std::min(o.top_level, depth) : std::min(depth, 7);
-        build_top_table(node, s->top_level, top);
-        rc = dev_alloc((void **)&s->d_node, node.size() * sizeof(int32_t));
+        std::vector<int32_t> blocks;
+        if (!build_walk(node, depth, s->top_level, top, blocks, err)) rc = fail(MCRT_EINVAL, err);
+        node.swap(blocks); // the kernel walks the blocks
+        if (node.empty()) node.assign(1, 0);
+        if (!rc) rc = dev_alloc((void **)&s->d_node, node.size() * sizeof(int32_t));
         if (!rc) rc = dev_alloc((void **)&s->d_top, top.size() * sizeof(int32_t));
         if (!rc) {
             hipError_t e = hipMemcpy(s->d_node, node.data(), node.size() * sizeof(int32_t), hipMemcpyHostToDevice);

@@ -164,19 +164,55 @@ inline int encode_octree(int64_t n_nodes, const int32_t *first_child, int64_t n_
     return depth;
 }
 
-// Dense top table of the octree at level top_level: for each block the
-// deepest node at or above that level containing it, stored as that node's
-// own entry so the walk starts one load further down: (level << 27) | first
-// child for an internal node, 1 << 31 | (level << 27) | cell for a leaf
-// (level <= 15; node and cell indices below 2^27).
-inline void build_top_table(const std::vector<int32_t> &node, int top_level, std::vector<int32_t> &top)
+// The leaf walk of the transport kernel.  A dense top table at level
+// top_level, then blocks of 64 entries that each cover the two levels below an
+// internal node (4 x 4 x 4 sub-cubes, index i + 4 j + 16 k): one dependent
+// load per two tree levels.  An entry is either a leaf, 1 << 31 | (level << 27)
+// | cell, or the index of the next block (below 2^25).  A leaf one level below
+// the node fills its 8 sub-cubes; a node one level above the deepest leaves
+// gets a block whose lower sub-cube bit is a copy (the walk reads it as 0).
+// Returns false (with a message) if the blocks would not fit 32-bit indices.
+inline uint32_t walk_leaf(int level, int32_t val) { return (1u << 31) | ((uint32_t)level << 27) | (uint32_t)(-val - 1); }
+
+inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_level, std::vector<int32_t> &top,
+                       std::vector<int32_t> &blocks, std::string &err)
 {
-    int T = 1 << top_level;
+    blocks.clear();
+    // block of internal node nd at level L; returns its index
+    std::vector<std::pair<int32_t, int>> work; // (node, level) of blocks still to fill
+    auto new_block = [&](int32_t nd, int level) -> uint32_t {
+        const size_t b = blocks.size() / 64;
+        blocks.resize(blocks.size() + 64, 0);
+        work.push_back({nd, level});
+        return (uint32_t)b;
+    };
+    auto fill = [&](size_t b, int32_t nd, int level) {
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i) {
+                    const int c1 = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
+                    const int32_t m1 = node[(size_t)nd] + c1;
+                    const int32_t e1 = node[(size_t)m1];
+                    uint32_t e;
+                    if (e1 < 0) {
+                        e = walk_leaf(level + 1, e1);
+                    } else {
+                        const int c2 = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+                        const int32_t m2 = e1 + c2;
+                        const int32_t e2 = node[(size_t)m2];
+                        e = e2 < 0 ? walk_leaf(level + 2, e2) : new_block(m2, level + 2);
+                    }
+                    blocks[b * 64 + (size_t)(i + 4 * j + 16 * k)] = (int32_t)e;
+                }
+    };
+    const int T = 1 << top_level;
     top.assign((size_t)T * T * T, 0);
+    std::vector<int32_t> block_of((size_t)node.size(), -1);
     for (int bz = 0; bz < T; ++bz)
         for (int by = 0; by < T; ++by)
             for (int bx = 0; bx < T; ++bx) {
-                int nd = 0, level = 0;
+                int32_t nd = 0;
+                int level = 0;
                 while (level < top_level && node[(size_t)nd] >= 0) {
                     int bit = top_level - 1 - level;
                     int child = ((bx >> bit) & 1) + 2 * ((by >> bit) & 1) + 4 * ((bz >> bit) & 1);
@@ -184,10 +220,25 @@ inline void build_top_table(const std::vector<int32_t> &node, int top_level, std
                     level++;
                 }
                 const int32_t val = node[(size_t)nd];
-                const uint32_t e = val >= 0 ? ((uint32_t)level << 27) | (uint32_t)val
-                                            : (1u << 31) | ((uint32_t)level << 27) | (uint32_t)(-val - 1);
+                uint32_t e;
+                if (val < 0) {
+                    e = walk_leaf(level, val);
+                } else {
+                    if (block_of[(size_t)nd] < 0) block_of[(size_t)nd] = (int32_t)new_block(nd, level);
+                    e = (uint32_t)block_of[(size_t)nd];
+                }
                 top[((size_t)bz * T + by) * T + bx] = (int32_t)e;
             }
+    (void)depth;
+    for (size_t w = 0; w < work.size(); ++w) {
+        if (blocks.size() >= (size_t(1) << 31)) {
+            err = "octree: walk blocks exceed 2^31 entries";
+            return false;
+        }
+        const auto [nd, level] = work[w];
+        fill(w, nd, level);
+    }
+    return true;
 }
 
 // Brick shape for the Cartesian storage layout: 32 cells per brick (one

@@ -132,8 +132,8 @@ template <typename Real, typename ImgT, int G> struct View {
     int top_level;  // octree: level of the dense top table
     Real lo[3], hi[3], cs[3];
     const float *density;
-    const int *node;     // octree: >= 0 first child, < 0 -(leaf + 1)
-    const int *top;      // octree: (level << 27) | node for each top-table block
+    const int *node;     // octree: the leaf walk's blocks of 64 entries (top table entries likewise)
+    const int *top;      // octree: the walk's entry for each top-table block
     long long n_cells;
     // Cartesian storage layout: bricks of 2^bs[0] x 2^bs[1] x 2^bs[2] = 32 cells,
     // nb[] bricks per axis; n_store = cells per wavelength slice incl. padding
@@ -420,20 +420,20 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
             if (!exits) ln.tn2 = next_plane_t(v, ln, 2);
         }
     } else {
-        // locate the leaf holding lattice point ci: dense top table, then descend
+        // locate the leaf holding lattice point ci: dense top table, then one
+        // load per two levels (blocks of 4 x 4 x 4 sub-cubes)
         const int sh = v.depth - v.top_level;
         const int T = 1 << v.top_level;
-        const uint32_t packed = (uint32_t)v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
-        int level = (int)((packed >> 27) & 15u);
-        const int pay = (int)(packed & ((1u << 27) - 1));
-        int val = (packed >> 31) ? -pay - 1 : pay; // the block's node entry
-        while (val >= 0) {
-            int bit = v.depth - 1 - level;
-            int child = ((ln.c0 >> bit) & 1) + 2 * ((ln.c1 >> bit) & 1) + 4 * ((ln.c2 >> bit) & 1);
-            val = v.node[val + child];
-            level++;
+        uint32_t e = (uint32_t)v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
+        int lv = v.top_level;
+        while (!(e >> 31)) {
+            const int s = v.depth - 1 - lv;
+            const int i = (((ln.c0 << 1) >> s) & 3) + 4 * (((ln.c1 << 1) >> s) & 3) + 16 * (((ln.c2 << 1) >> s) & 3);
+            e = (uint32_t)v.node[((long long)e << 6) + i];
+            lv += 2;
         }
-        cell = -val - 1;
+        const int level = (int)((e >> 27) & 15u);
+        cell = (int)(e & ((1u << 27) - 1));
         const int size = 1 << (v.depth - level);
         int o[3];
         Real tn[3];

@@ -106,6 +106,7 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         v.lo[a] = (Real)s->box[a];
         v.hi[a] = (Real)s->box[3 + a];
         v.cs[a] = (Real)((s->box[3 + a] - s->box[a]) / (double)v.n[a]);
+        v.ics[a] = (Real)((double)v.n[a] / (s->box[3 + a] - s->box[a]));
     }
     std::vector<float> stored;
     v.n_store = s->n_cells;

@@ -618,6 +618,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         v.lo[c] = (Real)g->box[c];
         v.hi[c] = (Real)g->box[3 + c];
         v.cs[c] = (Real)((g->box[3 + c] - g->box[c]) / (double)g->n[c]);
+        v.ics[c] = (Real)((double)g->n[c] / (g->box[3 + c] - g->box[c]));
     }
     v.depth = s->depth;
     v.top_level = s->top_level;
@@ -786,6 +787,7 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
             v.lo[c] = (Real)g->box[c];
             v.hi[c] = (Real)g->box[3 + c];
             v.cs[c] = (Real)((g->box[3 + c] - g->box[c]) / (double)g->n[c]);
+            v.ics[c] = (Real)((double)g->n[c] / (g->box[3 + c] - g->box[c]));
             v.src_pos[c] = (Real)s->source->pos[c];
         }
         v.density = s->d_density;

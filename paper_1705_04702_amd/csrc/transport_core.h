@@ -131,6 +131,7 @@ template <typename Real, typename ImgT, int G> struct View {
     int depth;      // octree maximum depth
     int top_level;  // octree: level of the dense top table
     Real lo[3], hi[3], cs[3];
+    Real ics[3]; // 1 / cs (FP32 octree steps multiply; FP64 divides)
     const float *density;
     const int *node;     // octree: the leaf walk's blocks of 64 entries (top table entries likewise)
     const int *top;      // octree: the walk's entry for each top-table block
@@ -455,21 +456,17 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
             am = 2;
         }
         te = rmax(tmin, ln.t);
+        // the stepped axis moves to the next cube; the others take the
+        // lattice cell of the exit point, clamped to the leaf (selects: the
+        // lanes of a wave step different axes)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (a == am) {
-                int q = ln.d[a] > Real(0) ? o[a] + size : o[a] - 1;
-                exits = q < 0 || q >= v.n[a];
-                cidx(ln, a) = q;
-            } else {
-                Real p = ln.r[a] + te * ln.d[a];
-                Real qf = floor((p - v.lo[a]) / v.cs[a]);
-                int qi;
-                if (qf < Real(o[a])) qi = o[a];
-                else if (qf > Real(o[a] + size - 1)) qi = o[a] + size - 1;
-                else qi = (int)qf;
-                cidx(ln, a) = qi;
-            }
+            const int q = ln.d[a] > Real(0) ? o[a] + size : o[a] - 1;
+            const Real p = ln.r[a] + te * ln.d[a];
+            const Real qf = floor(Prec<Real>::over_k(p - v.lo[a], v.cs[a], v.ics[a]));
+            const int qi = qf < Real(o[a]) ? o[a] : (qf > Real(o[a] + size - 1) ? o[a] + size - 1 : (int)qf);
+            exits = exits || (a == am && (q < 0 || q >= v.n[a]));
+            cidx(ln, a) = a == am ? q : qi;
         }
         if (++ln.steps >= v.octree_guard) {
             exits = true;

@@ -307,6 +307,35 @@ int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count);
 /* Image of instrument ins, layout [lambda][y][x], flux units; count >=
  * n_lambda * ny * nx. */
 int mcrt_result_image(const mcrt_result *res, int32_t ins, double *out, size_t count);
+/* SED of instrument ins: out[l] = total flux of wavelength slice l (the sum
+ * of its pixels, flux units, reduced on the device in FP64 in a fixed order);
+ * count >= n_lambda.  (Section 3.2, writing: SEDs next to the data cubes.) */
+int mcrt_result_sed(const mcrt_result *res, int32_t ins, double *out, size_t count);
+/* Writing phase (Section 3.2): the data cube of instrument ins as a FITS file
+ * (fits_path; layout as mcrt_fits_cube_create) and its SED as a text file
+ * (sed_path, as mcrt_sed_write_text); either path may be NULL.  Needs the
+ * medium's wavelengths (MCRT_EINVAL without them).  Files are overwritten. */
+int mcrt_result_write(const mcrt_result *res, int32_t ins, const char *fits_path, const char *sed_path);
+
+/* ---- Output files (host only: no device is touched) ----
+ * A data cube with one wavelength axis and two spatial axes whose wavelength
+ * slices may be produced in pieces, as the wavelength-sliced data cube of
+ * Section 5.2 (ParallelDatacube class).
+ * mcrt_fits_cube_create writes a FITS file: a primary HDU with BITPIX -64 and
+ * NAXIS1 = nx (x fastest), NAXIS2 = ny, NAXIS3 = n_lambda, all zero, and an
+ * IMAGE extension WAVELENGTHS holding lambda_um[n_lambda] (micron).
+ * mcrt_fits_cube_write_slices writes slices [first, first + count) of such a
+ * file in place from slices[count][ny][nx] (host FP64, row-major); the file
+ * must have been created with the same shape (MCRT_EINVAL otherwise).
+ * Different slice ranges may be written by different callers, one at a time
+ * per range; the caller keeps ownership of every array. */
+int mcrt_fits_cube_create(const char *path, int64_t nx, int64_t ny, int32_t n_lambda, const double *lambda_um);
+int mcrt_fits_cube_write_slices(const char *path, int64_t nx, int64_t ny, int32_t n_lambda, int32_t first,
+                                int32_t count, const double *slices);
+/* Text SED: two comment lines, then one line "lambda_um flux" per wavelength
+ * (17 significant digits). */
+int mcrt_sed_write_text(const char *path, int32_t n_lambda, const double *lambda_um, const double *sed);
+
 /* Energy sums (FP64): emitted = absorbed + escaped + truncated. */
 int mcrt_result_energy(const mcrt_result *res, double *emitted, double *absorbed,
                        double *escaped, double *truncated);

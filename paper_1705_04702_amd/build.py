@@ -32,6 +32,7 @@ UNITS = [
     ("proposal.hip", ["-x", "hip"]),
     ("microbench.hip", ["-x", "hip"]),
     ("mcrt_api.cpp", []),
+    ("output.cpp", []),
 ]
 
 

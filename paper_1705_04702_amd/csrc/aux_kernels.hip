@@ -103,4 +103,35 @@ hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double sc
 template hipError_t launch_image_scale<float>(const float *, double *, int64_t, double, hipStream_t);
 template hipError_t launch_image_scale<double>(const double *, double *, int64_t, double, hipStream_t);
 
+// SED of an instrument: sed[l] = scale * sum over the pixels of wavelength
+// slice l.  One block per slice; each thread sums a fixed stride of pixels in
+// FP64, then a fixed-shape tree in LDS, so the result does not depend on
+// timing.
+template <typename ImgT>
+__global__ void __launch_bounds__(256) sed_kernel(const ImgT *img, double *sed, int64_t npix, double scale)
+{
+    __shared__ double part[256];
+    const ImgT *row = img + (int64_t)blockIdx.x * npix;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < npix; i += 256) acc += (double)row[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sed[blockIdx.x] = part[0] * scale;
+}
+
+template <typename ImgT>
+hipError_t launch_sed(const ImgT *img, double *sed, int n_lambda, int64_t npix, double scale, hipStream_t stream)
+{
+    if (n_lambda <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sed_kernel<ImgT>, dim3((unsigned)n_lambda), dim3(256), 0, stream, img, sed, npix, scale);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sed<float>(const float *, double *, int, int64_t, double, hipStream_t);
+template hipError_t launch_sed<double>(const double *, double *, int, int64_t, double, hipStream_t);
+
 } // namespace mcrt

@@ -46,6 +46,9 @@ hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store
                                  int64_t ncell, hipStream_t stream);
 template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);
+// sed[l] = scale * sum of the npix pixels of slice l (n_lambda slices)
+template <typename ImgT>
+hipError_t launch_sed(const ImgT *img, double *sed, int n_lambda, int64_t npix, double scale, hipStream_t stream);
 
 } // namespace mcrt
 

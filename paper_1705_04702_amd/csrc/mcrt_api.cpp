@@ -73,6 +73,11 @@ bool finite_box(const double b[6])
 
 } // namespace
 
+namespace mcrt {
+// Error reporting for the other host sources of the library (output.cpp).
+int report_error(int code, const std::string &msg) { return fail(code, msg); }
+} // namespace mcrt
+
 struct mcrt_context {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -1096,6 +1101,55 @@ int mcrt_result_image(const mcrt_result *res, int32_t ins, double *out, size_t c
     dev_free(tmp);
     if (e != hipSuccess) return fail(MCRT_EDEVICE, std::string("result_image: ") + hipGetErrorString(e));
     return MCRT_OK;
+}
+
+int mcrt_result_sed(const mcrt_result *res, int32_t ins, double *out, size_t count)
+{
+    if (!res || !out) return fail(MCRT_EINVAL, "result_sed: NULL argument");
+    const mcrt_sim *s = res->sim;
+    if (ins < 0 || ins >= s->n_ins) return fail(MCRT_EINVAL, "result_sed: no such instrument");
+    const int nl = s->medium->n_lambda;
+    if (count < (size_t)nl) return fail(MCRT_EINVAL, "result_sed: output buffer too small");
+    const int64_t npix = (int64_t)s->ins[ins].npix[0] * s->ins[ins].npix[1];
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    double *tmp = nullptr;
+    int rc = dev_alloc((void **)&tmp, (size_t)nl * sizeof(double));
+    if (rc) return rc;
+    hipError_t e;
+    if (s->opt.precision == MCRT_FP32)
+        e = launch_sed<float>((const float *)res->d_images + s->ins_offset[ins], tmp, nl, npix, s->inv4pid2[ins], st);
+    else
+        e = launch_sed<double>((const double *)res->d_images + s->ins_offset[ins], tmp, nl, npix, s->inv4pid2[ins], st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, (size_t)nl * sizeof(double), hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dev_free(tmp);
+    if (e != hipSuccess) return fail(MCRT_EDEVICE, std::string("result_sed: ") + hipGetErrorString(e));
+    return MCRT_OK;
+}
+
+int mcrt_result_write(const mcrt_result *res, int32_t ins, const char *fits_path, const char *sed_path)
+{
+    if (!res) return fail(MCRT_EINVAL, "result_write: NULL result");
+    const mcrt_sim *s = res->sim;
+    if (ins < 0 || ins >= s->n_ins) return fail(MCRT_EINVAL, "result_write: no such instrument");
+    const int nl = s->medium->n_lambda;
+    if ((int)s->medium->lambda_um.size() != nl)
+        return fail(MCRT_EINVAL, "result_write: the medium was created without wavelengths");
+    const int64_t nx = s->ins[ins].npix[0], ny = s->ins[ins].npix[1];
+    int rc = MCRT_OK;
+    if (fits_path) {
+        std::vector<double> cube((size_t)(nl * nx * ny));
+        rc = mcrt_result_image(res, ins, cube.data(), cube.size());
+        if (!rc) rc = mcrt_fits_cube_create(fits_path, nx, ny, nl, s->medium->lambda_um.data());
+        if (!rc) rc = mcrt_fits_cube_write_slices(fits_path, nx, ny, nl, 0, nl, cube.data());
+    }
+    if (!rc && sed_path) {
+        std::vector<double> sed((size_t)nl);
+        rc = mcrt_result_sed(res, ins, sed.data(), sed.size());
+        if (!rc) rc = mcrt_sed_write_text(sed_path, nl, s->medium->lambda_um.data(), sed.data());
+    }
+    return rc;
 }
 
 int mcrt_result_energy(const mcrt_result *res, double *emitted, double *absorbed, double *escaped, double *truncated)

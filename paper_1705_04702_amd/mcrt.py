@@ -37,6 +37,8 @@ EXPORTS = [
     "mcrt_proposal_grad", "mcrt_sim_set_proposal", "mcrt_proposal_collect", "mcrt_histories_info",
     "mcrt_histories_records", "mcrt_histories_samples", "mcrt_histories_destroy",
     "mcrt_train_opts_default", "mcrt_proposal_train", "mcrt_proposal_eval",
+    "mcrt_result_sed", "mcrt_result_write", "mcrt_fits_cube_create", "mcrt_fits_cube_write_slices",
+    "mcrt_sed_write_text",
 ]
 MLP_PARAMS = 7400
 
@@ -162,6 +164,13 @@ def lib():
         "mcrt_train_opts_default": (None, [ctypes.POINTER(TrainOpts)]),
         "mcrt_proposal_train": (ctypes.c_int, [P, P, ctypes.POINTER(TrainOpts), DP]),
         "mcrt_proposal_eval": (ctypes.c_int, [P, P, DP]),
+        "mcrt_result_sed": (ctypes.c_int, [P, ctypes.c_int32, P, ctypes.c_size_t]),
+        "mcrt_result_write": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p]),
+        "mcrt_fits_cube_create": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                 P]),
+        "mcrt_fits_cube_write_slices": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64,
+                                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]),
+        "mcrt_sed_write_text": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -192,6 +201,32 @@ def microbench(kind: str, nbytes: int, n_ops: int = 1 << 28, device: int = 0) ->
     if rc != OK:
         raise MCRTError(rc, lib().mcrt_microbench_error().decode())
     return r.value
+
+
+def fits_cube_create(path, nx: int, ny: int, lambda_um) -> None:
+    """Creates a FITS data cube [n_lambda][ny][nx] of zeros with a WAVELENGTHS
+    extension (host only)."""
+    lam = np.ascontiguousarray(lambda_um, dtype=np.float64)
+    _check(lib().mcrt_fits_cube_create(os.fsencode(path), int(nx), int(ny), lam.size,
+                                       ctypes.c_void_p(lam.ctypes.data)))
+
+
+def fits_cube_write_slices(path, n_lambda: int, first: int, slices) -> None:
+    """Writes slices[count][ny][nx] at wavelength slices [first, first + count)."""
+    a = np.ascontiguousarray(slices, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("slices must be [count][ny][nx]")
+    _check(lib().mcrt_fits_cube_write_slices(os.fsencode(path), a.shape[2], a.shape[1], int(n_lambda), int(first),
+                                             a.shape[0], ctypes.c_void_p(a.ctypes.data)))
+
+
+def sed_write_text(path, lambda_um, sed) -> None:
+    lam = np.ascontiguousarray(lambda_um, dtype=np.float64)
+    f = np.ascontiguousarray(sed, dtype=np.float64)
+    if f.shape != lam.shape:
+        raise ValueError("lambda_um and sed differ in length")
+    _check(lib().mcrt_sed_write_text(os.fsencode(path), lam.size, ctypes.c_void_p(lam.ctypes.data),
+                                     ctypes.c_void_p(f.ctypes.data)))
 
 
 def default_options(**kw) -> Options:
@@ -259,6 +294,17 @@ class Result:
 
     def images(self) -> List[np.ndarray]:
         return [self.image(j) for j in range(len(self.sim.image_shapes))]
+
+    def sed(self, j: int) -> np.ndarray:
+        """Total flux per wavelength of instrument j (sum of its pixels)."""
+        out = np.empty(self.sim.n_lambda, dtype=np.float64)
+        _check(lib().mcrt_result_sed(self.h, int(j), ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def write(self, j: int, fits_path=None, sed_path=None):
+        """Writes instrument j's data cube (FITS) and/or SED (text)."""
+        enc = lambda p: None if p is None else os.fsencode(p)
+        _check(lib().mcrt_result_write(self.h, int(j), enc(fits_path), enc(sed_path)))
 
     def energy(self) -> np.ndarray:
         e = [ctypes.c_double() for _ in range(4)]

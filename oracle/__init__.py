@@ -69,6 +69,7 @@ class _Scene(ctypes.Structure):
         ("r_out", ctypes.c_double),
         ("lam_feature", ctypes.POINTER(ctypes.c_double)),
         ("rho_mean", ctypes.c_double),
+        ("dust_cdf", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -124,6 +125,14 @@ def lib():
         L.or_rotate.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double)]
         L.or_rotate.restype = None
+        L.or_dust_emission.argtypes = [ctypes.POINTER(_Scene), ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.or_dust_emission.restype = ctypes.c_int
+        L.or_planck.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_planck.restype = ctypes.c_double
+        L.or_bin_widths.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.or_bin_widths.restype = None
         _lib = L
     return _lib
 
@@ -132,7 +141,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-_SOURCES = {"point_iso": 0, "point_aniso": 1, "expdisk": 2}
+_SOURCES = {"point_iso": 0, "point_aniso": 1, "expdisk": 2, "dust": 3}
 
 
 class _SceneHolder:
@@ -179,6 +188,9 @@ class _SceneHolder:
         s.tau_peel_max = float(sc.tau_peel_max)
         self.lambdas = np.ascontiguousarray(sc.lambdas, dtype=np.float64)
         s.lambda_um = _ptr(self.lambdas, ctypes.c_double)
+        if sc.source == "dust":
+            self.dust_cdf = np.ascontiguousarray(sc.dust_cdf, dtype=np.float64)
+            s.dust_cdf = _ptr(self.dust_cdf, ctypes.c_double)
         self.s = s
 
 
@@ -238,6 +250,63 @@ def run(scene, n_per_lambda: int, seed: int = 0, first_id: int = 0, count=None,
         res["hist"] = hist.reshape(-1, histories, 14)
         res["hist_total"] = htot
     return res
+
+
+# ---------------------------------------------------------------------------
+# Dust emission phase and self-absorption cycles (Section 3.2), Cartesian grids
+# ---------------------------------------------------------------------------
+def planck(lambda_um, T):
+    return lib().or_planck(float(lambda_um), float(T))
+
+
+def bin_widths(lambda_um):
+    lam = np.ascontiguousarray(lambda_um, dtype=np.float64)
+    w = np.zeros_like(lam)
+    lib().or_bin_widths(_ptr(lam, ctypes.c_double), lam.size, _ptr(w, ctypes.c_double))
+    return w
+
+
+def dust_emission(scene, table, T0: float = 20.0, beta: float = 2.0):
+    """Cell temperatures [n_cells] and emission [n_cells, n_lambda] from an
+    absorbed-luminosity table [n_cells, n_lambda] (or_dust_emission)."""
+    h = _SceneHolder(scene)
+    tab = np.ascontiguousarray(table, dtype=np.float64)
+    T = np.zeros(h.s.n_cells)
+    emis = np.zeros((h.s.n_cells, h.s.n_lambda))
+    rc = lib().or_dust_emission(ctypes.byref(h.s), _ptr(tab, ctypes.c_double), float(T0), float(beta),
+                                _ptr(T, ctypes.c_double), _ptr(emis, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle or_dust_emission failed with code {rc}")
+    return T, emis
+
+
+def dust_scene(scene, emis):
+    """The scene with its source replaced by the dust emission emis [n_cells,
+    n_lambda]: running sums over the cells per wavelength, luminosity per
+    wavelength = the last running sum."""
+    cdf = np.ascontiguousarray(np.cumsum(np.asarray(emis, dtype=np.float64).T, axis=1))
+    sc = type(scene)(**{**scene.__dict__})
+    sc.source = "dust"
+    sc.lum = cdf[:, -1].copy()
+    sc.dust_cdf = cdf
+    return sc
+
+
+def self_absorption(scene, stellar_table, n_per_lambda: int, seed: int, cycles: int, T0: float = 20.0,
+                    beta: float = 2.0):
+    """Dust self-absorption cycles: cycle k (k = 1..cycles) emits from the
+    stellar plus the previous cycle's dust absorption and runs its packets
+    with seed + k - 1.  Returns per cycle (dust luminosity per wavelength,
+    the cycle's run result)."""
+    dust_abs = np.zeros_like(np.asarray(stellar_table))
+    out = []
+    for k in range(1, cycles + 1):
+        _, emis = dust_emission(scene, np.asarray(stellar_table) + dust_abs, T0, beta)
+        sc = dust_scene(scene, emis)
+        r = run(sc, n_per_lambda, seed=seed + k - 1)
+        out.append((sc.lum, r))
+        dust_abs = r["table"]
+    return out
 
 
 def mlp_forward(theta, f):

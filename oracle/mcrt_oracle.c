@@ -852,6 +852,22 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
         r[0] = R * cphi;
         r[1] = R * sphi;
         r[2] = z;
+    } else if (s->source_type == OR_SRC_DUST) {
+        /* the emitting cell: the first whose running sum exceeds u times the
+         * total (bisection), then a uniform point inside it */
+        const double *cdf = s->dust_cdf + (int64_t)ell * s->n_cells;
+        const double x = U(0) * cdf[s->n_cells - 1];
+        int64_t lo = 0, hi = s->n_cells - 1;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > x) hi = mid;
+            else lo = mid + 1;
+        }
+        int64_t idx[3] = {lo % s->n[0], (lo / s->n[0]) % s->n[1], lo / ((int64_t)s->n[0] * s->n[1])};
+        for (int a = 0; a < 3; ++a) {
+            double width = (s->box[3 + a] - s->box[a]) / (double)s->n[a];
+            r[a] = s->box[a] + ((double)idx[a] + U(1 + a)) * width;
+        }
     } else {
         r[0] = s->src_pos[0];
         r[1] = s->src_pos[1];
@@ -871,7 +887,8 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
     double L = L0;
     int use_phys = 1;
     mixture mx;
-    if (learned && s->source_type != OR_SRC_EXPDISK) {
+    const int point = s->source_type == OR_SRC_POINT_ISO || s->source_type == OR_SRC_POINT_ANISO;
+    if (learned && point) {
         double f[9], out[40];
         event_features(s, ell, r, NULL, 0.0, f);
         or_mlp_forward(s->mlp, f, out);
@@ -894,7 +911,7 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
         k[1] = st * sphi;
         k[2] = mu;
     }
-    if (learned && s->source_type != OR_SRC_EXPDISK) {
+    if (learned && point) {
         double S = s->source_type == OR_SRC_POINT_ANISO ? 2.0 * fabs(k[2]) : 1.0;
         double pphys = S / (4.0 * OR_PI);
         double q = s->alpha * pphys + (1.0 - s->alpha) * mixture_vmf_pdf(&mx, k);
@@ -1076,6 +1093,76 @@ static void feature_constants(or_scene *s, double *lam_feature)
     s->lam_feature = lam_feature;
 }
 
+/* ---------------------------------------------------------------------------
+ * Dust emission (Section 3.2, dust emission and self-absorption phases; the
+ * paper's dust model files are not available, so a modified blackbody stands
+ * in): every cell re-emits the luminosity it absorbed, with the spectral
+ * shape kappa_abs B_lambda(T) dlambda and a temperature fixed by its heating.
+ * ------------------------------------------------------------------------- */
+double or_planck(double lambda_um, double T)
+{
+    const double h = 6.62607015e-34, c = 2.99792458e8, k = 1.380649e-23; /* SI, exact */
+    const double lam = lambda_um * 1e-6;
+    const double x = h * c / (lam * k * T);
+    return 2.0 * h * c * c / (lam * lam * lam * lam * lam) / or_expm1(x);
+}
+
+void or_bin_widths(const double *lambda_um, int32_t n, double *width)
+{
+    if (n == 1) {
+        width[0] = lambda_um[0];
+        return;
+    }
+    /* bin edges: geometric means of neighbours; the outer edges mirror the
+     * inner ones in log lambda */
+    for (int32_t l = 0; l < n; ++l) {
+        double lo = l > 0 ? sqrt(lambda_um[l - 1] * lambda_um[l])
+                          : lambda_um[0] * lambda_um[0] / sqrt(lambda_um[0] * lambda_um[1]);
+        double hi = l + 1 < n ? sqrt(lambda_um[l] * lambda_um[l + 1])
+                              : lambda_um[n - 1] * lambda_um[n - 1] / sqrt(lambda_um[n - 2] * lambda_um[n - 1]);
+        width[l] = hi - lo;
+    }
+}
+
+int or_dust_emission(const or_scene *s, const double *table, double T0, double beta, double *T, double *emis)
+{
+    if (!s || !table || !T || !emis || s->grid_type != OR_GRID_CARTESIAN || !s->lambda_um || s->n_lambda < 1 ||
+        !(T0 > 0.0) || !(beta > -4.0))
+        return -1;
+    const int64_t nc = s->n_cells;
+    const int32_t nl = s->n_lambda;
+    double *width = (double *)malloc((size_t)nl * sizeof(double));
+    double *shape = (double *)malloc((size_t)nl * sizeof(double));
+    or_bin_widths(s->lambda_um, nl, width);
+    /* cells have equal volume: mass in units of cell volume */
+    double mass = 0.0, absorbed = 0.0;
+    for (int64_t m = 0; m < nc; ++m) {
+        mass += (double)s->density[m];
+        for (int32_t l = 0; l < nl; ++l) absorbed += table[m * nl + l];
+    }
+    const double u0 = mass > 0.0 ? absorbed / mass : 0.0;
+    for (int64_t m = 0; m < nc; ++m) {
+        double La = 0.0;
+        for (int32_t l = 0; l < nl; ++l) La += table[m * nl + l];
+        const double rho = (double)s->density[m];
+        T[m] = 0.0;
+        for (int32_t l = 0; l < nl; ++l) emis[m * nl + l] = 0.0;
+        if (!(La > 0.0) || !(rho > 0.0) || !(u0 > 0.0)) continue;
+        const double Tm = T0 * or_exp(or_log((La / rho) / u0) / (4.0 + beta));
+        T[m] = Tm;
+        double sum = 0.0;
+        for (int32_t l = 0; l < nl; ++l) {
+            shape[l] = s->kappa[l] * (1.0 - s->albedo[l]) * width[l] * or_planck(s->lambda_um[l], Tm);
+            sum += shape[l];
+        }
+        if (!(sum > 0.0)) continue; /* nothing the grid's bins can carry */
+        for (int32_t l = 0; l < nl; ++l) emis[m * nl + l] = La * (shape[l] / sum);
+    }
+    free(width);
+    free(shape);
+    return 0;
+}
+
 int or_run(const or_scene *s_in, uint64_t n_per_lambda, uint64_t first_id,
            uint64_t count, uint64_t seed, uint32_t model, or_out *out)
 {
@@ -1087,6 +1174,7 @@ int or_run(const or_scene *s_in, uint64_t n_per_lambda, uint64_t first_id,
     if (s->lambda_um && s->n_lambda > 0) feature_constants(s, lam_feature);
     if (first_id + count > 0xffffffffull + 1ull) return -1;
     if (s->n_lambda <= 0 || s->n_cells <= 0 || s->n_ins < 0) return -1;
+    if (s->source_type == OR_SRC_DUST && (s->grid_type != OR_GRID_CARTESIAN || !s->dust_cdf)) return -1;
     runctx c;
     memset(&c, 0, sizeof(c));
     c.s = s;

@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { OR_GRID_CARTESIAN = 0, OR_GRID_OCTREE = 1 };
-enum { OR_SRC_POINT_ISO = 0, OR_SRC_POINT_ANISO = 1, OR_SRC_EXPDISK = 2 };
+enum { OR_SRC_POINT_ISO = 0, OR_SRC_POINT_ANISO = 1, OR_SRC_EXPDISK = 2, OR_SRC_DUST = 3 };
 
 /* One scene.  All arrays are borrowed (the caller owns them). */
 typedef struct {
@@ -57,6 +57,10 @@ typedef struct {
     double r_out;
     const double *lam_feature;
     double rho_mean;
+    /* OR_SRC_DUST (Cartesian grids): [n_lambda][n_cells] running sums over the
+     * cells (natural order ix + nx (iy + ny iz)) of the dust emission, from
+     * or_dust_emission; lum[] holds each row's last element */
+    const double *dust_cdf;
 } or_scene;
 
 typedef struct {
@@ -97,6 +101,22 @@ typedef struct {
  * the Philox counter.  Returns 0, or a negative value on invalid input. */
 int or_run(const or_scene *scene, uint64_t n_per_lambda, uint64_t first_id,
            uint64_t count, uint64_t seed, uint32_t model, or_out *out);
+
+/* Dust emission of a Cartesian grid (stand-in for the dust emission and
+ * self-absorption phases of Section 3.2): from the absorbed luminosity table
+ * [n_cells][n_lambda], each cell's temperature T = T0 (u / u0)^(1 / (4 + beta))
+ * with u = absorbed luminosity per unit mass and u0 = total absorbed / total
+ * mass, and its emission spread over the wavelength bins in proportion to
+ * kappa (1 - albedo) B_lambda(T) dlambda (bin widths between the geometric
+ * means of neighbouring wavelengths), so that every cell emits what it
+ * absorbed.  Writes T[n_cells] (0 where nothing is absorbed) and
+ * emis[n_cells][n_lambda].  Returns 0, or -1 (octree or invalid input). */
+int or_dust_emission(const or_scene *scene, const double *table, double T0, double beta, double *T,
+                     double *emis);
+/* Planck spectral radiance B_lambda(T) in W m^-2 m^-1 sr^-1, lambda in micron. */
+double or_planck(double lambda_um, double T);
+/* Widths of the wavelength bins around lambda_um[n] (n >= 1). */
+void or_bin_widths(const double *lambda_um, int32_t n, double *width);
 
 /* Building blocks exposed for the pin tests. */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -68,6 +68,7 @@ typedef struct mcrt_sim mcrt_sim;
 typedef struct mcrt_result mcrt_result;
 typedef struct mcrt_proposal mcrt_proposal;
 typedef struct mcrt_histories mcrt_histories;
+typedef struct mcrt_dust mcrt_dust;
 
 typedef struct {
     int32_t precision;     /* MCRT_FP32 or MCRT_FP64_VALIDATE */
@@ -316,6 +317,55 @@ int mcrt_result_sed(const mcrt_result *res, int32_t ins, double *out, size_t cou
  * (sed_path, as mcrt_sed_write_text); either path may be NULL.  Needs the
  * medium's wavelengths (MCRT_EINVAL without them).  Files are overwritten. */
 int mcrt_result_write(const mcrt_result *res, int32_t ins, const char *fits_path, const char *sed_path);
+
+/* ---- Dust emission phase (Section 3.2: dust emission and self-absorption
+ * phases).  The paper's dust model files are not available; a modified
+ * blackbody stands in.  Cartesian grids only (MCRT_EINVAL otherwise).
+ *
+ * A cell m that absorbed La(m) (summed over wavelengths) re-emits exactly
+ * La(m), spread over the wavelength bins l in proportion to
+ *     kappa_l (1 - albedo_l) dlambda_l B_lambda(lambda_l, T_m),
+ * dlambda_l the bin width between the geometric means of neighbouring
+ * wavelengths (outer edges mirrored in log lambda), B_lambda the Planck
+ * function, and T_m = T0 (u_m / u0)^(1 / (4 + beta)), u_m = La(m) / density
+ * and u0 = total absorbed / total density (the temperature of a grain whose
+ * emissivity goes as lambda^-beta, in units where heating u0 gives T0).
+ * Dust packets start at a uniform point of a cell drawn in proportion to its
+ * emission at the packet's wavelength (Philox slot 0 for the cell, 1-3 for
+ * the point, 5-6 for the isotropic direction), with L0 = the wavelength's
+ * dust luminosity / n_per_lambda, and then follow the stellar packets' life
+ * cycle (absorption, forced scattering, peel-offs). */
+typedef struct {
+    double T0;   /* temperature (K) at the mean heating; default 20 */
+    double beta; /* emissivity index, > -4; default 2 */
+} mcrt_dust_params;
+void mcrt_dust_params_default(mcrt_dust_params *p);
+/* Emission of sim's cells from the sum of the absorption tables of
+ * absorbed[0 .. n-1] (1 <= n <= 4, results of sim; they must not be running).
+ * Computed on the device in FP64 (a fixed-order reduction and scan: the same
+ * result on every call); needs the medium's wavelengths.  The handle holds
+ * n_lambda x n_cells FP64 running sums on the device until destroyed. */
+int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t n, const mcrt_dust_params *params,
+                     mcrt_dust **out);
+/* Emitted luminosity per wavelength (count >= n_lambda). */
+int mcrt_dust_luminosity(const mcrt_dust *dust, double *L, size_t count);
+/* Cell temperatures in natural cell order (0 where nothing is absorbed);
+ * count >= n_cells; host or device buffer. */
+int mcrt_dust_temperature(const mcrt_dust *dust, double *T, size_t count);
+void mcrt_dust_destroy(mcrt_dust *dust);
+/* Runs dust packet ids [first_id, first_id + count) of every wavelength into
+ * res, as mcrt_run_into (same errors; MCRT_EINVAL with a learned proposal). */
+int mcrt_run_dust_into(mcrt_sim *sim, const mcrt_dust *dust, uint64_t n_per_lambda, uint64_t first_id,
+                       uint64_t count, uint64_t seed, mcrt_result *res);
+/* Self-absorption cycles: cycle k = 1, 2, ... emits from the stellar
+ * absorption plus the previous cycle's dust absorption and runs n_per_lambda
+ * dust packets per wavelength with seed + k - 1 into a fresh result; stops
+ * after max_cycles or when the total dust luminosity changed by at most
+ * tol relative to the previous cycle.  Returns the last cycle's emission and
+ * result (owned by the caller) and the number of cycles run. */
+int mcrt_dust_self_absorption(mcrt_sim *sim, const mcrt_result *stellar, const mcrt_dust_params *params,
+                              uint64_t n_per_lambda, uint64_t seed, int32_t max_cycles, double tol,
+                              mcrt_dust **dust_out, mcrt_result **result_out, int32_t *cycles_done);
 
 /* ---- Output files (host only: no device is touched) ----
  * A data cube with one wavelength axis and two spatial axes whose wavelength

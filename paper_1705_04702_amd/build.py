@@ -31,6 +31,7 @@ UNITS = [
     ("aux_kernels.hip", ["-x", "hip"]),
     ("proposal.hip", ["-x", "hip"]),
     ("microbench.hip", ["-x", "hip"]),
+    ("dust.hip", ["-x", "hip", "-ffp-contract=off"]),
     ("mcrt_api.cpp", []),
     ("output.cpp", []),
 ]

@@ -46,6 +46,31 @@ hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store
                                  int64_t ncell, hipStream_t stream);
 template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);
+// Dust emission of a Cartesian grid (dust.hip).  Cells in natural order
+// m = ix + nx (iy + ny iz); tables and density in the bricked storage order.
+struct DustGrid {
+    long long n_cells, n_store;
+    int n_lambda;
+    int n[3], bs[3], sh[3], nb[3];
+};
+struct DustTables {
+    const double *t[4]; // absorption tables [n_lambda][n_store], summed
+    int n;
+};
+int dust_blocks(long long n_cells);    // blocks of the per-cell kernels (partial sums)
+int dust_scan_tiles(long long n);       // tiles per row of the scan
+// absorbed[m] = sum over wavelengths of the summed tables; part_* per block
+hipError_t launch_dust_absorbed(const DustGrid &g, const DustTables &tabs, const float *density, double *absorbed,
+                                double *part_abs, double *part_mass, hipStream_t st);
+// T[m] and emis[l][m] (see dust.hip)
+hipError_t launch_dust_emission(const DustGrid &g, const double *absorbed, const float *density,
+                                const double *lambda_um, const double *kw, double u0, double T0, double beta,
+                                double *T, double *emis, hipStream_t st);
+// x[rows][n] := inclusive running sums of each row; tile_sums[rows][tiles]
+hipError_t launch_dust_scan(double *x, long long n, int rows, double *tile_sums, hipStream_t st);
+// guide[rows][K]: first index whose running sum exceeds k (row total / K)
+hipError_t launch_dust_guide(const double *cdf, long long n, int K, int rows, int *guide, hipStream_t st);
+
 // sed[l] = scale * sum of the npix pixels of slice l (n_lambda slices)
 template <typename ImgT>
 hipError_t launch_sed(const ImgT *img, double *sed, int n_lambda, int64_t npix, double scale, hipStream_t stream);

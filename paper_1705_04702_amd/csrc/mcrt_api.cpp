@@ -165,6 +165,16 @@ struct mcrt_histories {
     double c_sum = 0.0;
 };
 
+struct mcrt_dust {
+    mcrt_sim *sim = nullptr;
+    mcrt_dust_params params{};
+    int K = 0;                   // guide entries per wavelength
+    double *d_cdf = nullptr;     // [n_lambda][n_cells] running sums of the emission
+    int *d_guide = nullptr;      // [n_lambda][K]
+    double *d_T = nullptr;       // [n_cells] temperatures
+    std::vector<double> L;       // emitted luminosity per wavelength
+};
+
 struct mcrt_result {
     mcrt_sim *sim = nullptr;
     double *d_table = nullptr;    // [n_lambda][n_cells]
@@ -597,7 +607,7 @@ int mcrt_result_create(mcrt_sim *sim, mcrt_result **out)
 
 template <typename Real, typename ImgT, int G>
 static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
-                    mcrt_result *r, mcrt_histories *hist = nullptr)
+                    mcrt_result *r, mcrt_histories *hist = nullptr, const mcrt_dust *dust = nullptr)
 {
     const mcrt_medium *m = s->medium;
     const mcrt_grid *g = m->grid;
@@ -607,7 +617,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         optics[l].kappa = (Real)m->kappa[l];
         optics[l].albedo = (Real)m->albedo[l];
         optics[l].g = (Real)m->g[l];
-        optics[l].L0 = (Real)(s->source->L[l] / (double)n_per_lambda);
+        optics[l].L0 = (Real)((dust ? dust->L[l] : s->source->L[l]) / (double)n_per_lambda);
         optics[l].lamf = (Real)s->lamf[l];
     }
     HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
@@ -634,7 +644,12 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     v.n_store = s->n_store;
     v.n_lambda = m->n_lambda;
     v.optics = nullptr;
-    v.src_type = s->source->type;
+    v.src_type = dust ? (int)kDust : s->source->type;
+    if (dust) {
+        v.dust_cdf = dust->d_cdf;
+        v.dust_guide = dust->d_guide;
+        v.dust_K = dust->K;
+    }
     for (int c = 0; c < 3; ++c) v.src_pos[c] = (Real)s->source->pos[c];
     v.hR = (Real)s->source->hR;
     v.zs = (Real)s->source->zs;
@@ -743,6 +758,216 @@ int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint6
     }
     if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res);
     return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res);
+}
+
+// ---------------------------------------------------------------------------
+// Dust emission phase (Section 3.2): emission of a Cartesian sim's cells from
+// the absorbed luminosity of one or more of its results, and runs of dust
+// packets.
+// ---------------------------------------------------------------------------
+void mcrt_dust_params_default(mcrt_dust_params *p)
+{
+    if (!p) return;
+    p->T0 = 20.0;
+    p->beta = 2.0;
+}
+
+void mcrt_dust_destroy(mcrt_dust *d)
+{
+    if (!d) return;
+    (void)hipSetDevice(d->sim->ctx->device);
+    dev_free(d->d_cdf);
+    dev_free(d->d_guide);
+    dev_free(d->d_T);
+    delete d;
+}
+
+int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t n, const mcrt_dust_params *params,
+                     mcrt_dust **out)
+{
+    if (!sim || !out || (n > 0 && !absorbed)) return fail(MCRT_EINVAL, "dust_create: NULL argument");
+    *out = nullptr;
+    if (n < 1 || n > 4) return fail(MCRT_EINVAL, "dust_create: between 1 and 4 absorption results");
+    const mcrt_medium *m = sim->medium;
+    const mcrt_grid *g = m->grid;
+    if (g->type != kCartesian) return fail(MCRT_EINVAL, "dust_create: dust emission needs a Cartesian grid");
+    if ((int)m->lambda_um.size() != m->n_lambda)
+        return fail(MCRT_EINVAL, "dust_create: the medium was created without wavelengths");
+    for (int i = 0; i < n; ++i)
+        if (!absorbed[i] || absorbed[i]->sim != sim) return fail(MCRT_EINVAL, "dust_create: result of another sim");
+    mcrt_dust_params p;
+    mcrt_dust_params_default(&p);
+    if (params) p = *params;
+    if (!(p.T0 > 0.0) || !std::isfinite(p.T0) || !(p.beta > -4.0) || !std::isfinite(p.beta))
+        return fail(MCRT_EINVAL, "dust_create: T0 must be positive and beta > -4");
+    if (g->n_cells >= (int64_t(1) << 31)) return fail(MCRT_EINVAL, "dust_create: too many cells");
+    if (m->n_lambda > 65535) return fail(MCRT_EINVAL, "dust_create: at most 65535 wavelengths");
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    hipStream_t st = sim->ctx->stream;
+    const int nl = m->n_lambda;
+    const long long nc = g->n_cells;
+    mcrt_dust *d = new mcrt_dust();
+    d->sim = sim;
+    d->params = p;
+    d->K = (int)std::min<long long>(std::max<long long>(nc / 16, 1), 1 << 16);
+    // bin widths between the geometric means of neighbouring wavelengths
+    std::vector<double> kw((size_t)nl);
+    const std::vector<double> &lam = m->lambda_um;
+    for (int l = 0; l < nl; ++l) {
+        double w;
+        if (nl == 1) {
+            w = lam[0];
+        } else {
+            const double lo = l > 0 ? std::sqrt(lam[l - 1] * lam[l]) : lam[0] * lam[0] / std::sqrt(lam[0] * lam[1]);
+            const double hi = l + 1 < nl ? std::sqrt(lam[l] * lam[l + 1])
+                                         : lam[nl - 1] * lam[nl - 1] / std::sqrt(lam[nl - 2] * lam[nl - 1]);
+            w = hi - lo;
+        }
+        kw[l] = m->kappa[l] * (1.0 - m->albedo[l]) * w;
+    }
+    DustGrid dg{};
+    dg.n_cells = nc;
+    dg.n_store = sim->n_store;
+    dg.n_lambda = nl;
+    for (int a = 0; a < 3; ++a) {
+        dg.n[a] = g->n[a];
+        dg.bs[a] = sim->bs[a];
+        dg.sh[a] = sim->sh[a];
+        dg.nb[a] = sim->nb[a];
+    }
+    DustTables tabs{};
+    tabs.n = n;
+    for (int i = 0; i < n; ++i) tabs.t[i] = absorbed[i]->d_table;
+    const int blocks = dust_blocks(nc), tiles = dust_scan_tiles(nc);
+    double *d_abs = nullptr, *d_part = nullptr, *d_lam = nullptr, *d_kw = nullptr, *d_tiles = nullptr;
+    int rc = dev_alloc((void **)&d->d_cdf, (size_t)nl * (size_t)nc * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d->d_guide, (size_t)nl * (size_t)d->K * sizeof(int));
+    if (!rc) rc = dev_alloc((void **)&d->d_T, (size_t)nc * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_abs, (size_t)nc * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_part, 2 * (size_t)blocks * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_lam, (size_t)nl * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_kw, (size_t)nl * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_tiles, (size_t)nl * (size_t)tiles * sizeof(double));
+    hipError_t e = hipSuccess;
+    std::vector<double> part(2 * (size_t)blocks);
+    if (!rc) {
+        e = hipMemcpyAsync(d_lam, lam.data(), (size_t)nl * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_kw, kw.data(), (size_t)nl * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = launch_dust_absorbed(dg, tabs, sim->d_density, d_abs, d_part, d_part + blocks, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(part.data(), d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (!rc && e == hipSuccess) {
+        double absorbed_total = 0.0, mass = 0.0;
+        for (int b = 0; b < blocks; ++b) {
+            absorbed_total += part[(size_t)b];
+            mass += part[(size_t)blocks + b];
+        }
+        const double u0 = mass > 0.0 ? absorbed_total / mass : 0.0;
+        e = launch_dust_emission(dg, d_abs, sim->d_density, d_lam, d_kw, u0, p.T0, p.beta, d->d_T, d->d_cdf, st);
+        if (e == hipSuccess) e = launch_dust_scan(d->d_cdf, nc, nl, d_tiles, st);
+        if (e == hipSuccess) e = launch_dust_guide(d->d_cdf, nc, d->K, nl, d->d_guide, st);
+        d->L.assign((size_t)nl, 0.0);
+        for (int l = 0; l < nl && e == hipSuccess; ++l)
+            e = hipMemcpyAsync(&d->L[(size_t)l], d->d_cdf + (size_t)l * (size_t)nc + (size_t)(nc - 1), sizeof(double),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    dev_free(d_abs);
+    dev_free(d_part);
+    dev_free(d_lam);
+    dev_free(d_kw);
+    dev_free(d_tiles);
+    if (!rc && e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("dust_create: ") + hipGetErrorString(e));
+    if (rc) {
+        mcrt_dust_destroy(d);
+        return rc;
+    }
+    *out = d;
+    return MCRT_OK;
+}
+
+int mcrt_dust_luminosity(const mcrt_dust *d, double *L, size_t count)
+{
+    if (!d || !L) return fail(MCRT_EINVAL, "dust_luminosity: NULL argument");
+    if (count < d->L.size()) return fail(MCRT_EINVAL, "dust_luminosity: output buffer too small");
+    std::copy(d->L.begin(), d->L.end(), L);
+    return MCRT_OK;
+}
+
+int mcrt_dust_temperature(const mcrt_dust *d, double *T, size_t count)
+{
+    if (!d || !T) return fail(MCRT_EINVAL, "dust_temperature: NULL argument");
+    const size_t nc = (size_t)d->sim->medium->grid->n_cells;
+    if (count < nc) return fail(MCRT_EINVAL, "dust_temperature: output buffer too small");
+    HIP_TRY(hipSetDevice(d->sim->ctx->device));
+    HIP_TRY(hipMemcpyAsync(T, d->d_T, nc * sizeof(double), hipMemcpyDefault, d->sim->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(d->sim->ctx->stream));
+    return MCRT_OK;
+}
+
+int mcrt_run_dust_into(mcrt_sim *sim, const mcrt_dust *dust, uint64_t n_per_lambda, uint64_t first_id,
+                       uint64_t count, uint64_t seed, mcrt_result *res)
+{
+    if (!sim || !dust || !res) return fail(MCRT_EINVAL, "run_dust_into: NULL argument");
+    if (dust->sim != sim || res->sim != sim) return fail(MCRT_EINVAL, "run_dust_into: dust or result of another sim");
+    if (sim->prop) return fail(MCRT_EINVAL, "run_dust_into: the learned proposal is for point sources");
+    if (n_per_lambda == 0 || n_per_lambda > (uint64_t(1) << 32))
+        return fail(MCRT_EINVAL, "run_dust_into: n_per_lambda must be in 1 .. 2^32");
+    if (first_id > n_per_lambda || count > n_per_lambda - first_id)
+        return fail(MCRT_EINVAL, "run_dust_into: id range exceeds n_per_lambda");
+    BusyGuard guard(sim->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "run_dust_into: the simulation is already running");
+    if (count == 0) return MCRT_OK;
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    if (sim->opt.precision == MCRT_FP32)
+        return run_impl<float, float, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
+    return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
+}
+
+int mcrt_dust_self_absorption(mcrt_sim *sim, const mcrt_result *stellar, const mcrt_dust_params *params,
+                              uint64_t n_per_lambda, uint64_t seed, int32_t max_cycles, double tol, mcrt_dust **dust_out,
+                              mcrt_result **result_out, int32_t *cycles_done)
+{
+    if (!sim || !stellar || !dust_out || !result_out) return fail(MCRT_EINVAL, "dust_self_absorption: NULL argument");
+    *dust_out = nullptr;
+    *result_out = nullptr;
+    if (max_cycles < 1 || !(tol >= 0.0)) return fail(MCRT_EINVAL, "dust_self_absorption: max_cycles >= 1, tol >= 0");
+    mcrt_dust *dust = nullptr;
+    mcrt_result *prev = nullptr;
+    double Lprev = 0.0;
+    int rc = MCRT_OK, k = 0;
+    for (k = 1; k <= max_cycles; ++k) {
+        const mcrt_result *src[2] = {stellar, prev};
+        mcrt_dust *dk = nullptr;
+        rc = mcrt_dust_create(sim, src, prev ? 2 : 1, params, &dk);
+        if (rc) break;
+        mcrt_dust_destroy(dust);
+        dust = dk;
+        mcrt_result *rk = nullptr;
+        rc = mcrt_result_create(sim, &rk);
+        if (rc) break;
+        rc = mcrt_run_dust_into(sim, dust, n_per_lambda, 0, n_per_lambda, seed + (uint64_t)(k - 1), rk);
+        mcrt_result_destroy(prev);
+        prev = rk;
+        if (rc && rc != MCRT_ELIMIT) break;
+        double L = 0.0;
+        for (double x : dust->L) L += x;
+        const bool converged = k > 1 && std::fabs(L - Lprev) <= tol * L;
+        Lprev = L;
+        if (converged) break;
+    }
+    if (rc && rc != MCRT_ELIMIT) {
+        mcrt_dust_destroy(dust);
+        mcrt_result_destroy(prev);
+        return rc;
+    }
+    *dust_out = dust;
+    *result_out = prev;
+    if (cycles_done) *cycles_done = k > max_cycles ? max_cycles : k;
+    return rc;
 }
 
 template <typename Real, typename ImgT>

@@ -42,7 +42,7 @@ constexpr int kMlpParams = 7400; // 9 -> 64 -> 64 -> 40
 constexpr int kHistFloats = 14;  // features (9), new direction (3), luminosity, flux so far
 
 enum GridType : int { kCartesian = 0, kOctree = 1 };
-enum SourceType : int { kPointIso = 0, kPointAniso = 1, kExpDisk = 2 };
+enum SourceType : int { kPointIso = 0, kPointAniso = 1, kExpDisk = 2, kDust = 3 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): counter (block, packet, wavelength,
@@ -147,6 +147,13 @@ template <typename Real, typename ImgT, int G> struct View {
     int src_type;
     Real src_pos[3];
     Real hR, zs;
+    // dust emission (kDust, Cartesian): per wavelength the running sums of the
+    // cells' emission in natural cell order [n_lambda][n_cells], and a guide
+    // of dust_K entries per wavelength: guide[k] = first cell whose running
+    // sum exceeds k total / K
+    const double *dust_cdf;
+    const int *dust_guide;
+    int dust_K;
     // instruments
     int n_ins;
     const InsDesc<Real> *ins;
@@ -932,10 +939,43 @@ MCRT_HD void scatter(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty)
 
 // After the emission peel-offs: the emission direction (already sampled, or
 // left to the learned proposal for point sources), then the first propagation.
+// Point sources take the learned proposal at emission; extended sources
+// (disk, dust) sample their own emission direction.
+template <typename Real, typename ImgT, int G> MCRT_HD bool point_source(const View<Real, ImgT, G> &v)
+{
+    return v.src_type == kPointIso || v.src_type == kPointAniso;
+}
+
+// Dust emission: the first cell (natural order) whose running sum exceeds
+// u times the wavelength's total.  The guide brackets the answer between
+// guide[k - 1] and guide[k + 2], k = floor(x K / total), then bisection.
+template <typename Real, typename ImgT, int G>
+MCRT_HD long long dust_cell(const View<Real, ImgT, G> &v, uint32_t lam, double u)
+{
+    const long long n = v.n_cells;
+    const double *cdf = v.dust_cdf + (long long)lam * n;
+    const double total = cdf[n - 1];
+    if (!(total > 0.0)) return n - 1;
+    const double x = u * total;
+    const int K = v.dust_K;
+    const int *guide = v.dust_guide + (long long)lam * K;
+    const double step = total / (double)K;
+    double q = x / step;
+    int k = q < (double)K ? (int)q : K - 1;
+    long long lo = k > 0 ? guide[k - 1] : 0;
+    long long hi = k + 2 < K ? guide[k + 2] : n - 1;
+    while (lo < hi) {
+        const long long mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
 template <typename Sink, typename Real, typename ImgT, int G>
 MCRT_HD void emission_done(const View<Real, ImgT, G> &v, Lane<Real> &ln)
 {
-    if (learned_on<Sink>(v) && v.src_type != kExpDisk) {
+    if (learned_on<Sink>(v) && point_source(v)) {
         ln.mode = kDead;
         ln.parked = true;
         ln.emis_dir = true;
@@ -963,7 +1003,20 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.parked = false;
     ln.opt = v.optics[lam];
     Stream st = stream_of(v, ln);
-    if (v.src_type == kExpDisk) {
+    // dust sources exist on Cartesian grids in the plain kernels only
+    constexpr bool kDustOn = G == kCartesian && !Sink::kLearn && !Sink::kHist;
+    if (kDustOn && v.src_type == kDust) {
+        // the emitting cell, then a uniform point inside it
+        Real u0, u1, u2, u3;
+        st.template pair<Real>(0, u0, u1);
+        st.template pair<Real>(1, u2, u3);
+        const long long m = dust_cell(v, lam, (double)u0);
+        const long long nxy = (long long)v.n[0] * v.n[1];
+        const int ix = (int)(m % v.n[0]), iy = (int)((m / v.n[0]) % v.n[1]), iz = (int)(m / nxy);
+        ln.r[0] = v.lo[0] + ((Real)ix + u1) * v.cs[0];
+        ln.r[1] = v.lo[1] + ((Real)iy + u2) * v.cs[1];
+        ln.r[2] = v.lo[2] + ((Real)iz + u3) * v.cs[2];
+    } else if (v.src_type == kExpDisk) {
         Real u0, u1, u2, u3;
         st.template pair<Real>(0, u0, u1);
         st.template pair<Real>(1, u2, u3);
@@ -980,7 +1033,7 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
         ln.r[1] = v.src_pos[1];
         ln.r[2] = v.src_pos[2];
     }
-    if (!(learned_on<Sink>(v) && v.src_type != kExpDisk)) {
+    if (!(learned_on<Sink>(v) && point_source(v))) {
         Real u4, u5, u6, u7;
         st.template pair<Real>(2, u4, u5);
         st.template pair<Real>(3, u6, u7);

@@ -38,7 +38,8 @@ EXPORTS = [
     "mcrt_histories_records", "mcrt_histories_samples", "mcrt_histories_destroy",
     "mcrt_train_opts_default", "mcrt_proposal_train", "mcrt_proposal_eval",
     "mcrt_result_sed", "mcrt_result_write", "mcrt_fits_cube_create", "mcrt_fits_cube_write_slices",
-    "mcrt_sed_write_text",
+    "mcrt_sed_write_text", "mcrt_dust_params_default", "mcrt_dust_create", "mcrt_dust_luminosity",
+    "mcrt_dust_temperature", "mcrt_dust_destroy", "mcrt_run_dust_into", "mcrt_dust_self_absorption",
 ]
 MLP_PARAMS = 7400
 
@@ -171,6 +172,16 @@ def lib():
         "mcrt_fits_cube_write_slices": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64,
                                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]),
         "mcrt_sed_write_text": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, P, P]),
+        "mcrt_dust_params_default": (None, [ctypes.POINTER(DustParams)]),
+        "mcrt_dust_create": (ctypes.c_int, [P, PP, ctypes.c_int32, ctypes.POINTER(DustParams), PP]),
+        "mcrt_dust_luminosity": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_dust_temperature": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "mcrt_dust_destroy": (None, [P]),
+        "mcrt_run_dust_into": (ctypes.c_int, [P, P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                              ctypes.c_uint64, P]),
+        "mcrt_dust_self_absorption": (ctypes.c_int, [P, P, ctypes.POINTER(DustParams), ctypes.c_uint64,
+                                                     ctypes.c_uint64, ctypes.c_int32, ctypes.c_double, PP, PP,
+                                                     ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -201,6 +212,45 @@ def microbench(kind: str, nbytes: int, n_ops: int = 1 << 28, device: int = 0) ->
     if rc != OK:
         raise MCRTError(rc, lib().mcrt_microbench_error().decode())
     return r.value
+
+
+class DustParams(ctypes.Structure):
+    _fields_ = [("T0", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+class Dust:
+    """Dust emission of a Cartesian sim's cells (device-resident running sums
+    of the emission per wavelength, temperatures)."""
+
+    def __init__(self, sim: "Sim", h):
+        self.sim = sim
+        self.h = h
+
+    def luminosity(self) -> np.ndarray:
+        out = np.empty(self.sim.n_lambda, dtype=np.float64)
+        _check(lib().mcrt_dust_luminosity(self.h, ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def temperature(self) -> np.ndarray:
+        out = np.empty(self.sim.n_cells, dtype=np.float64)
+        _check(lib().mcrt_dust_temperature(self.h, ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def close(self):
+        if self.h:
+            lib().mcrt_dust_destroy(self.h)
+            self.h = None
+        self.sim._dusts.discard(self)
+
+
+def dust_params(T0: Optional[float] = None, beta: Optional[float] = None) -> DustParams:
+    p = DustParams()
+    lib().mcrt_dust_params_default(ctypes.byref(p))
+    if T0 is not None:
+        p.T0 = float(T0)
+    if beta is not None:
+        p.beta = float(beta)
+    return p
 
 
 def fits_cube_create(path, nx: int, ny: int, lambda_um) -> None:
@@ -342,6 +392,7 @@ class Sim:
         self.ctx = ctx
         self.h = None
         self._results = weakref.WeakSet()
+        self._dusts = weakref.WeakSet()
         box = (ctypes.c_double * 6)(*[float(x) for x in scene.box])
         g = ctypes.c_void_p()
         if scene.grid_type == "octree":
@@ -430,10 +481,50 @@ class Sim:
         self.run_into(res, n_per_lambda, seed, first_id, count)
         return res
 
+    def dust(self, absorbed: Sequence[Result], T0: Optional[float] = None, beta: Optional[float] = None) -> Dust:
+        """Dust emission from the summed absorption of up to 4 results."""
+        arr = (ctypes.c_void_p * len(absorbed))(*[r.h for r in absorbed])
+        p = dust_params(T0, beta)
+        h = ctypes.c_void_p()
+        _check(lib().mcrt_dust_create(self.h, arr, len(absorbed), ctypes.byref(p), ctypes.byref(h)))
+        d = Dust(self, h)
+        self._dusts.add(d)
+        return d
+
+    def run_dust_into(self, dust: Dust, result: Result, n_per_lambda: int, seed: int = 0, first_id: int = 0,
+                      count: Optional[int] = None) -> int:
+        if count is None:
+            count = n_per_lambda - first_id
+        return _check(lib().mcrt_run_dust_into(self.h, dust.h, int(n_per_lambda), int(first_id), int(count),
+                                               int(seed), result.h), allow=(ELIMIT,))
+
+    def run_dust(self, dust: Dust, n_per_lambda: int, seed: int = 0) -> Result:
+        res = self.new_result()
+        self.run_dust_into(dust, res, n_per_lambda, seed)
+        return res
+
+    def self_absorption(self, stellar: Result, n_per_lambda: int, seed: int = 0, max_cycles: int = 10,
+                        tol: float = 1e-3, T0: Optional[float] = None, beta: Optional[float] = None):
+        """Self-absorption cycles (mcrt_dust_self_absorption): returns the last
+        cycle's (Dust, Result, cycles run)."""
+        p = dust_params(T0, beta)
+        d, r, k = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int32()
+        _check(lib().mcrt_dust_self_absorption(self.h, stellar.h, ctypes.byref(p), int(n_per_lambda), int(seed),
+                                               int(max_cycles), float(tol), ctypes.byref(d), ctypes.byref(r),
+                                               ctypes.byref(k)), allow=(ELIMIT,))
+        dust = Dust(self, d)
+        self._dusts.add(dust)
+        res = Result(self, r)
+        self._results.add(res)
+        return dust, res, int(k.value)
+
     def close(self):
-        """Destroys the sim's results first (a handle must outlive the handles
-        created from it), then the sim and its scene objects."""
+        """Destroys the sim's results and dust emissions first (a handle must
+        outlive the handles created from it), then the sim and its scene
+        objects."""
         L = lib()
+        for d in list(getattr(self, "_dusts", ())):
+            d.close()
         for r in list(getattr(self, "_results", ())):
             r.close()
         if getattr(self, "h", None):

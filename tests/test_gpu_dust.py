@@ -1,0 +1,112 @@
+"""Dust emission phase on the GPU (Section 3.2, dust emission and
+self-absorption phases) against the oracle: cell temperatures and emitted
+luminosity per wavelength, FP64 parity of the dust packets' transport, the
+self-absorption cycles, FP32 energy balance, and the error cases."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04702_amd import mcrt, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _disk():
+    return scenes.disk(n=(16, 16, 8), n_lambda=6, npix=16, tau_v_faceon=5.0)
+
+
+def _close(a, b, rtol=1e-9):
+    nz = b != 0
+    assert np.array_equal(a == 0, b == 0)
+    assert np.all(np.abs(a[nz] - b[nz]) <= rtol * np.abs(b[nz]))
+
+
+def test_dust_emission_matches_oracle():
+    sc = _disk()
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    st = sim.run(300, seed=1)
+    o = oracle.run(sc, 300, seed=1)
+    d = sim.dust([st], T0=25.0, beta=1.5)
+    T_o, em_o = oracle.dust_emission(sc, o["table"], T0=25.0, beta=1.5)
+    _close(d.temperature(), T_o, 1e-9)
+    assert np.allclose(d.luminosity(), em_o.sum(axis=0), rtol=1e-9, atol=0)
+    # every cell re-emits what it absorbed
+    assert d.luminosity().sum() == pytest.approx(st.table().sum(), rel=1e-12)
+    sim.close()
+    ctx.close()
+
+
+def test_dust_transport_fp64_parity():
+    sc = _disk()
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    st = sim.run(300, seed=1)
+    o = oracle.run(sc, 300, seed=1)
+    d = sim.dust([st])
+    r = sim.run_dust(d, 400, seed=9)
+    _, em_o = oracle.dust_emission(sc, o["table"])
+    od = oracle.run(oracle.dust_scene(sc, em_o), 400, seed=9)
+    _close(r.table(), od["table"])
+    for a, b in zip(r.images(), od["images"]):
+        _close(a, b)
+    assert np.allclose(r.energy(), od["energy"], rtol=1e-9)
+    sim.close()
+    ctx.close()
+
+
+def test_self_absorption_cycles_match_oracle():
+    sc = _disk()
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    st = sim.run(200, seed=1)
+    o = oracle.run(sc, 200, seed=1)
+    d, r, k = sim.self_absorption(st, 150, seed=4, max_cycles=3, tol=0.0)
+    assert k == 3
+    cyc = oracle.self_absorption(sc, o["table"], 150, seed=4, cycles=3)
+    L_o, r_o = cyc[-1]
+    assert np.allclose(d.luminosity(), L_o, rtol=1e-9, atol=0)
+    _close(r.table(), r_o["table"], 1e-8)
+    # a loose tolerance stops after the second cycle
+    d2, r2, k2 = sim.self_absorption(st, 150, seed=4, max_cycles=5, tol=0.5)
+    assert k2 == 2
+    sim.close()
+    ctx.close()
+
+
+def test_dust_fp32_energy_balance_and_flux():
+    sc = scenes.disk(n=(32, 32, 16), n_lambda=8, npix=32, tau_v_faceon=5.0)
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    st = sim.run(20000, seed=1)
+    d = sim.dust([st])
+    r = sim.run_dust(d, 20000, seed=2)
+    e = r.energy()
+    assert e[0] == pytest.approx(d.luminosity().sum(), rel=1e-5)
+    assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+    sim.close()
+    ctx.close()
+
+
+def test_dust_errors():
+    ctx = mcrt.Context(0)
+    tor = scenes.torus(5, 4, 2, 16, n_clumps=10)
+    so = mcrt.Sim(ctx, tor, mcrt.FP64_VALIDATE)
+    ro = so.run(20, seed=0)
+    with pytest.raises(mcrt.MCRTError):
+        so.dust([ro])                      # octree grid
+    so.close()
+    sc = _disk()
+    s1 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    s2 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
+    r2 = s2.run(20, seed=0)
+    with pytest.raises(mcrt.MCRTError):
+        s1.dust([r2])                      # result of another sim
+    r1 = s1.run(20, seed=0)
+    with pytest.raises(mcrt.MCRTError):
+        s1.dust([r1], T0=-1.0)
+    with pytest.raises(mcrt.MCRTError):
+        s1.dust([])
+    s1.close()
+    s2.close()
+    ctx.close()

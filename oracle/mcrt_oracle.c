@@ -841,6 +841,11 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
     or_out *o = c->out;
     const double kappa = s->kappa[ell], albedo = s->albedo[ell], g = s->hg_g[ell];
 #define U(slot) or_uniform64(c->seed, id, (uint32_t)ell, c->model, (uint32_t)(slot))
+    /* a packet without luminosity adds zero to every tally: it ends at launch */
+    if (!(L0 > 0.0)) {
+        o->stats.packets++;
+        return 0;
+    }
     /* launch */
     double r[3], k[3];
     if (s->source_type == OR_SRC_EXPDISK) {

@@ -1053,8 +1053,10 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.e = 1;
     ty.emitted += (double)ln.L0;
     ty.packets++;
-    ln.mode = kLaunched;
     ln.marching = false;
+    // a packet without luminosity (a wavelength the source does not emit at)
+    // would add zero everywhere: it ends at launch
+    ln.mode = ln.L0 > Real(0) ? kLaunched : kDead;
 }
 
 // Handles the end of a march; leaves the lane marching again, dead, or

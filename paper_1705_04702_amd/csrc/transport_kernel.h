@@ -251,15 +251,14 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     }
     __syncthreads();
 
-    // Segments per march iteration: FP32 8 (Cartesian 4 and octree 2 with the
-    // learned proposal, whose network needs the registers), FP64 as the host
-    // simulator.  FP32 deposits are issued transposed through LDS:
+    // Segments per march iteration: FP32 8 (4 with the learned proposal,
+    // whose network needs the registers), FP64 as the host simulator.  FP32 deposits are issued transposed through LDS:
     // Cartesian runs hold their open run (16 slots per lane); octree runs and
     // the learned proposal (registers, LDS) take one slot per segment -- on
     // the octree's smaller tables the extra issue costs more than the held
     // runs save.
     constexpr int kK = sizeof(Real) != 4 ? BatchOf<G>::value
-                                         : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 2 : 8));
+                                         : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 4 : 8));
     constexpr int kTR = sizeof(Real) == 4 ? (G == kCartesian && !LEARN ? 16 : kK) : 0;
     typedef DevSink<LEARN, HIST, kTR, kK> SinkT;
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;

@@ -253,6 +253,8 @@ typedef struct {
     int depth;          /* maximum leaf depth D */
     int64_t lattice;    /* 2^D */
     int64_t *leaf_of_node; /* leaf index (depth-first order) or -1 */
+    int *leaf_level;       /* per leaf: its level */
+    int64_t *leaf_org;     /* per leaf: lattice origin (3 per leaf, lattice 2^D) */
 } geom;
 
 typedef struct {
@@ -298,9 +300,16 @@ static int geom_init(geom *g, const or_scene *s)
     g->leaf_of_node = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
     int64_t *stack_node = (int64_t *)malloc((size_t)(nn + 8) * sizeof(int64_t));
     int *stack_level = (int *)malloc((size_t)(nn + 8) * sizeof(int));
-    if (!g->leaf_of_node || !stack_node || !stack_level) {
+    /* node origins in units of the node's own level: child c of a node at
+     * (x, y, z) sits at (2x + bx, 2y + by, 2z + bz) */
+    int64_t *stack_org = (int64_t *)malloc((size_t)(nn + 8) * 3 * sizeof(int64_t));
+    g->leaf_level = (int *)malloc((size_t)(s->n_cells > 0 ? s->n_cells : 1) * sizeof(int));
+    int64_t *org_at_level = (int64_t *)malloc((size_t)(s->n_cells > 0 ? s->n_cells : 1) * 3 * sizeof(int64_t));
+    if (!g->leaf_of_node || !stack_node || !stack_level || !stack_org || !g->leaf_level || !org_at_level) {
         free(stack_node);
         free(stack_level);
+        free(stack_org);
+        free(org_at_level);
         return -1;
     }
     for (int64_t i = 0; i < nn; ++i) g->leaf_of_node[i] = -1;
@@ -308,34 +317,58 @@ static int geom_init(geom *g, const or_scene *s)
     int maxdepth = 0;
     stack_node[top] = 0;
     stack_level[top] = 0;
+    stack_org[0] = stack_org[1] = stack_org[2] = 0;
     top++;
     while (top > 0) {
         top--;
         int64_t node = stack_node[top];
         int level = stack_level[top];
+        const int64_t ox = stack_org[3 * top], oy = stack_org[3 * top + 1], oz = stack_org[3 * top + 2];
         int32_t fc = s->first_child[node];
         if (fc < 0) {
+            if (next_leaf < s->n_cells) {
+                g->leaf_level[next_leaf] = level;
+                org_at_level[3 * next_leaf] = ox;
+                org_at_level[3 * next_leaf + 1] = oy;
+                org_at_level[3 * next_leaf + 2] = oz;
+            }
             g->leaf_of_node[node] = next_leaf++;
             if (level > maxdepth) maxdepth = level;
         } else {
             for (int c = 7; c >= 0; --c) {
                 stack_node[top] = (int64_t)fc + c;
                 stack_level[top] = level + 1;
+                stack_org[3 * top] = 2 * ox + (c & 1);
+                stack_org[3 * top + 1] = 2 * oy + ((c >> 1) & 1);
+                stack_org[3 * top + 2] = 2 * oz + ((c >> 2) & 1);
                 top++;
             }
         }
     }
     free(stack_node);
     free(stack_level);
+    free(stack_org);
     g->depth = maxdepth;
     g->lattice = (int64_t)1 << maxdepth;
-    return next_leaf == s->n_cells ? 0 : -1;
+    if (next_leaf != s->n_cells) {
+        free(org_at_level);
+        return -1;
+    }
+    /* origins on the finest lattice */
+    for (int64_t m = 0; m < s->n_cells; ++m)
+        for (int a = 0; a < 3; ++a) org_at_level[3 * m + a] <<= (maxdepth - g->leaf_level[m]);
+    g->leaf_org = org_at_level;
+    return 0;
 }
 
 static void geom_free(geom *g)
 {
     free(g->leaf_of_node);
+    free(g->leaf_level);
+    free(g->leaf_org);
     g->leaf_of_node = NULL;
+    g->leaf_level = NULL;
+    g->leaf_org = NULL;
 }
 
 /* Index of the grid slice containing coordinate p along an axis with origin
@@ -868,10 +901,19 @@ static int one_packet(runctx *c, int ell, uint32_t id, double L0, int64_t slot)
             if (cdf[mid] > x) hi = mid;
             else lo = mid + 1;
         }
-        int64_t idx[3] = {lo % s->n[0], (lo / s->n[0]) % s->n[1], lo / ((int64_t)s->n[0] * s->n[1])};
-        for (int a = 0; a < 3; ++a) {
-            double width = (s->box[3 + a] - s->box[a]) / (double)s->n[a];
-            r[a] = s->box[a] + ((double)idx[a] + U(1 + a)) * width;
+        if (s->grid_type == OR_GRID_OCTREE) {
+            /* the leaf's cube on the 2^D lattice */
+            const int64_t size = (int64_t)1 << (c->g.depth - c->g.leaf_level[lo]);
+            for (int a = 0; a < 3; ++a) {
+                double width = (s->box[3 + a] - s->box[a]) / (double)c->g.lattice;
+                r[a] = s->box[a] + ((double)c->g.leaf_org[3 * lo + a] + U(1 + a) * (double)size) * width;
+            }
+        } else {
+            int64_t idx[3] = {lo % s->n[0], (lo / s->n[0]) % s->n[1], lo / ((int64_t)s->n[0] * s->n[1])};
+            for (int a = 0; a < 3; ++a) {
+                double width = (s->box[3 + a] - s->box[a]) / (double)s->n[a];
+                r[a] = s->box[a] + ((double)idx[a] + U(1 + a)) * width;
+            }
         }
     } else {
         r[0] = s->src_pos[0];
@@ -1131,29 +1173,36 @@ void or_bin_widths(const double *lambda_um, int32_t n, double *width)
 
 int or_dust_emission(const or_scene *s, const double *table, double T0, double beta, double *T, double *emis)
 {
-    if (!s || !table || !T || !emis || s->grid_type != OR_GRID_CARTESIAN || !s->lambda_um || s->n_lambda < 1 ||
-        !(T0 > 0.0) || !(beta > -4.0))
-        return -1;
+    if (!s || !table || !T || !emis || !s->lambda_um || s->n_lambda < 1 || !(T0 > 0.0) || !(beta > -4.0)) return -1;
     const int64_t nc = s->n_cells;
     const int32_t nl = s->n_lambda;
+    /* cell volumes: Cartesian cells all 1, an octree leaf at level L 8^-L
+     * (the box's volume) -- only ratios of masses matter */
+    geom g;
+    if (geom_init(&g, s)) {
+        geom_free(&g);
+        return -1;
+    }
     double *width = (double *)malloc((size_t)nl * sizeof(double));
     double *shape = (double *)malloc((size_t)nl * sizeof(double));
+    double *cmass = (double *)malloc((size_t)nc * sizeof(double));
     or_bin_widths(s->lambda_um, nl, width);
-    /* cells have equal volume: mass in units of cell volume */
     double mass = 0.0, absorbed = 0.0;
     for (int64_t m = 0; m < nc; ++m) {
-        mass += (double)s->density[m];
+        const double vol = s->grid_type == OR_GRID_OCTREE ? ldexp(1.0, -3 * g.leaf_level[m]) : 1.0;
+        cmass[m] = (double)s->density[m] * vol;
+        mass += cmass[m];
         for (int32_t l = 0; l < nl; ++l) absorbed += table[m * nl + l];
     }
     const double u0 = mass > 0.0 ? absorbed / mass : 0.0;
     for (int64_t m = 0; m < nc; ++m) {
         double La = 0.0;
         for (int32_t l = 0; l < nl; ++l) La += table[m * nl + l];
-        const double rho = (double)s->density[m];
+        const double mm = cmass[m];
         T[m] = 0.0;
         for (int32_t l = 0; l < nl; ++l) emis[m * nl + l] = 0.0;
-        if (!(La > 0.0) || !(rho > 0.0) || !(u0 > 0.0)) continue;
-        const double Tm = T0 * or_exp(or_log((La / rho) / u0) / (4.0 + beta));
+        if (!(La > 0.0) || !(mm > 0.0) || !(u0 > 0.0)) continue;
+        const double Tm = T0 * or_exp(or_log((La / mm) / u0) / (4.0 + beta));
         T[m] = Tm;
         double sum = 0.0;
         for (int32_t l = 0; l < nl; ++l) {
@@ -1165,6 +1214,8 @@ int or_dust_emission(const or_scene *s, const double *table, double T0, double b
     }
     free(width);
     free(shape);
+    free(cmass);
+    geom_free(&g);
     return 0;
 }
 
@@ -1179,7 +1230,7 @@ int or_run(const or_scene *s_in, uint64_t n_per_lambda, uint64_t first_id,
     if (s->lambda_um && s->n_lambda > 0) feature_constants(s, lam_feature);
     if (first_id + count > 0xffffffffull + 1ull) return -1;
     if (s->n_lambda <= 0 || s->n_cells <= 0 || s->n_ins < 0) return -1;
-    if (s->source_type == OR_SRC_DUST && (s->grid_type != OR_GRID_CARTESIAN || !s->dust_cdf)) return -1;
+    if (s->source_type == OR_SRC_DUST && !s->dust_cdf) return -1;
     runctx c;
     memset(&c, 0, sizeof(c));
     c.s = s;

@@ -57,8 +57,8 @@ typedef struct {
     double r_out;
     const double *lam_feature;
     double rho_mean;
-    /* OR_SRC_DUST (Cartesian grids): [n_lambda][n_cells] running sums over the
-     * cells (natural order ix + nx (iy + ny iz)) of the dust emission, from
+    /* OR_SRC_DUST: [n_lambda][n_cells] running sums over the cells (natural
+     * order ix + nx (iy + ny iz), or the leaf order) of the dust emission, from
      * or_dust_emission; lum[] holds each row's last element */
     const double *dust_cdf;
 } or_scene;
@@ -102,15 +102,17 @@ typedef struct {
 int or_run(const or_scene *scene, uint64_t n_per_lambda, uint64_t first_id,
            uint64_t count, uint64_t seed, uint32_t model, or_out *out);
 
-/* Dust emission of a Cartesian grid (stand-in for the dust emission and
- * self-absorption phases of Section 3.2): from the absorbed luminosity table
- * [n_cells][n_lambda], each cell's temperature T = T0 (u / u0)^(1 / (4 + beta))
- * with u = absorbed luminosity per unit mass and u0 = total absorbed / total
- * mass, and its emission spread over the wavelength bins in proportion to
- * kappa (1 - albedo) B_lambda(T) dlambda (bin widths between the geometric
- * means of neighbouring wavelengths), so that every cell emits what it
- * absorbed.  Writes T[n_cells] (0 where nothing is absorbed) and
- * emis[n_cells][n_lambda].  Returns 0, or -1 (octree or invalid input). */
+/* Dust emission (stand-in for the dust emission and self-absorption phases
+ * of Section 3.2): from the absorbed luminosity table [n_cells][n_lambda],
+ * each cell's temperature T = T0 (u / u0)^(1 / (4 + beta)) with u = absorbed
+ * luminosity per unit mass (mass = density x volume; octree leaves at level
+ * L have volume 8^-L of the box) and u0 = total absorbed / total mass, and
+ * its emission spread over the wavelength bins in proportion to kappa
+ * (1 - albedo) B_lambda(T) dlambda (bin widths between the geometric means of
+ * neighbouring wavelengths), so that every cell emits what it absorbed.
+ * Writes T[n_cells] (0 where nothing is absorbed) and emis[n_cells][n_lambda].
+ * Returns 0, or -1 on invalid input.  A dust packet starts at a uniform point
+ * of its cell (Cartesian cell or octree leaf). */
 int or_dust_emission(const or_scene *scene, const double *table, double T0, double beta, double *T,
                      double *emis);
 /* Planck spectral radiance B_lambda(T) in W m^-2 m^-1 sr^-1, lambda in micron. */

@@ -116,3 +116,55 @@ def test_self_absorption_cycles_conserve_energy():
     # the dust emits the stellar absorption plus its own: more after cycle 1
     assert cyc[1][0].sum() > cyc[0][0].sum()
     assert cyc[0][0].sum() == pytest.approx(st["table"].sum(), rel=1e-12)
+
+
+def _oct_scene(seed=3, depth=3, npix=8):
+    fc, leaves, D = scenes.random_octree(depth, 0.5, seed)
+    nl = leaves[0].shape[0]
+    sc = scenes.Scene(grid_type="octree", box=(-1.0, -1.0, -1.0, 1.0, 1.0, 1.0), first_child=fc,
+                      density=np.full(nl, 1e-9, np.float32), lambdas=np.array([1.0]), kappa=np.array([1.0]),
+                      albedo=np.array([0.0]), hg_g=np.array([0.0]), lum=np.array([1.0]), source="point_iso",
+                      instruments=[scenes.Instrument(0.0, 0.0, 100.0, (2.0, 2.0), (npix, npix))])
+    return sc, leaves, D
+
+
+def test_octree_temperature_weights_leaf_volume():
+    """Absorption proportional to leaf volume at uniform density is uniform
+    heating per unit mass: every leaf sits at T0."""
+    sc, (lv, lx, ly, lz), D = _oct_scene()
+    sc.lambdas = np.array([200.0])  # where an 18 K grain emits
+    assert len(set(lv.tolist())) > 1
+    table = (8.0 ** -lv.astype(np.float64))[:, None] * np.array([[3.0]])
+    T, em = oracle.dust_emission(sc, table, T0=18.0, beta=2.0)
+    assert np.allclose(T, 18.0, rtol=1e-13)
+    assert np.allclose(em[:, 0], table[:, 0], rtol=1e-13)
+
+
+def test_octree_dust_packets_start_in_their_leaf():
+    """Two emitting leaves of different size: the face-on image (one pixel
+    per finest lattice column) has flux only over their footprints, in the
+    ratio of their emission."""
+    sc, (lv, lx, ly, lz), D = _oct_scene(npix=8)
+    N = 1 << D
+    big = int(np.argmin(lv))
+    small = [m for m in range(lv.size) if lv[m] == lv.max()]
+    def foot(m):
+        size = 1 << (D - lv[m])
+        x0, y0 = lx[m] * size, ly[m] * size
+        px = np.zeros((N, N), bool)
+        # image x along world y, image y along -world x
+        for ix in range(x0, x0 + size):
+            for iy in range(y0, y0 + size):
+                px[N - 1 - ix, iy] = True
+        return px
+    fb = foot(big)
+    small = next(m for m in small if not (foot(m) & fb).any())
+    fs = foot(small)
+    emis = np.zeros((lv.size, 1))
+    emis[big, 0], emis[small, 0] = 1.0, 2.0
+    r = oracle.run(oracle.dust_scene(sc, emis), 20000, seed=11)
+    img = r["images"][0][0]
+    assert not img[~(fb | fs)].any()
+    assert img[fs].sum() / img[fb].sum() == pytest.approx(2.0, rel=0.05)
+    # within the big leaf's footprint the flux is spread over all its columns
+    assert (img[fb] > 0).all()

@@ -320,17 +320,19 @@ int mcrt_result_write(const mcrt_result *res, int32_t ins, const char *fits_path
 
 /* ---- Dust emission phase (Section 3.2: dust emission and self-absorption
  * phases).  The paper's dust model files are not available; a modified
- * blackbody stands in.  Cartesian grids only (MCRT_EINVAL otherwise).
+ * blackbody stands in.  Cartesian and octree grids.
  *
  * A cell m that absorbed La(m) (summed over wavelengths) re-emits exactly
  * La(m), spread over the wavelength bins l in proportion to
  *     kappa_l (1 - albedo_l) dlambda_l B_lambda(lambda_l, T_m),
  * dlambda_l the bin width between the geometric means of neighbouring
  * wavelengths (outer edges mirrored in log lambda), B_lambda the Planck
- * function, and T_m = T0 (u_m / u0)^(1 / (4 + beta)), u_m = La(m) / density
- * and u0 = total absorbed / total density (the temperature of a grain whose
- * emissivity goes as lambda^-beta, in units where heating u0 gives T0).
- * Dust packets start at a uniform point of a cell drawn in proportion to its
+ * function, and T_m = T0 (u_m / u0)^(1 / (4 + beta)) with
+ * u_m = La(m) / mass(m), mass = density x volume (Cartesian cells 1, an
+ * octree leaf at level L 8^-L of the box) and u0 = total absorbed / total
+ * mass (the temperature of a grain whose emissivity goes as lambda^-beta, in
+ * units where heating u0 gives T0).  Cells in natural order (octree: leaf
+ * order).  Dust packets start at a uniform point of a cell drawn in proportion to its
  * emission at the packet's wavelength (Philox slot 0 for the cell, 1-3 for
  * the point, 5-6 for the isotropic direction), with L0 = the wavelength's
  * dust luminosity / n_per_lambda, and then follow the stellar packets' life

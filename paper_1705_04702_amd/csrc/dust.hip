@@ -1,10 +1,10 @@
-// dust.hip -- the dust emission of a Cartesian grid on the device (Section
+// dust.hip -- the dust emission of a grid's cells on the device (Section
 // 3.2, dust emission and self-absorption phases; a modified blackbody stands
 // in for the paper's dust model files):
 //   1. per cell, the absorbed luminosity summed over the wavelengths of one or
-//      more absorption tables (bricked, wavelength-major) and per-block sums of
-//      it and of the density (the heating unit u0 = total absorbed / total
-//      mass);
+//      more absorption tables (wavelength-major) and per-block sums of it and
+//      of the mass, density x volume (Cartesian cells 1, octree leaves 8^-L;
+//      the heating unit u0 = total absorbed / total mass);
 //   2. per cell, the temperature T = T0 (u / u0)^(1 / (4 + beta)) and the
 //      emission of each wavelength bin, absorbed * kw B_lambda(T) / sum, with
 //      kw = kappa (1 - albedo) * bin width (the cell emits what it absorbed);
@@ -29,6 +29,7 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 __device__ __forceinline__ long long brick_index(const int n[3], const int bs[3], const int sh[3], const int nb[3],
                                                  long long m)
 {
+    // (octree leaves are stored in leaf order: callers use m itself)
     const int ix = (int)(m % n[0]), iy = (int)((m / n[0]) % n[1]), iz = (int)(m / ((long long)n[0] * n[1]));
     const long long brick = (ix >> bs[0]) + (long long)nb[0] * ((iy >> bs[1]) + (long long)nb[1] * (iz >> bs[2]));
     const int in = ((ix & ((1 << bs[0]) - 1)) << sh[0]) + ((iy & ((1 << bs[1]) - 1)) << sh[1]) +
@@ -58,13 +59,13 @@ absorbed_kernel(DustGrid g, DustTables tabs, const float *density, double *absor
     const long long m = (long long)blockIdx.x * kScanBlock + threadIdx.x;
     double La = 0.0, rho = 0.0;
     if (m < g.n_cells) {
-        const long long sidx = brick_index(g.n, g.bs, g.sh, g.nb, m);
+        const long long sidx = g.leaf ? m : brick_index(g.n, g.bs, g.sh, g.nb, m);
         for (int l = 0; l < g.n_lambda; ++l) {
             double t = tabs.t[0][(long long)l * g.n_store + sidx];
             for (int k = 1; k < tabs.n; ++k) t = t + tabs.t[k][(long long)l * g.n_store + sidx];
             La += t;
         }
-        rho = (double)density[sidx];
+        rho = (double)density[sidx] * (g.leaf ? ldexp(1.0, -3 * g.leaf[4 * m + 3]) : 1.0); // mass
         absorbed[m] = La;
     }
     const double sa = block_sum(La, part);
@@ -90,8 +91,8 @@ emission_kernel(DustGrid g, const double *absorbed, const float *density, const 
     const long long m = (long long)blockIdx.x * kScanBlock + threadIdx.x;
     if (m >= g.n_cells) return;
     const double La = absorbed[m];
-    const long long sidx = brick_index(g.n, g.bs, g.sh, g.nb, m);
-    const double rho = (double)density[sidx];
+    const long long sidx = g.leaf ? m : brick_index(g.n, g.bs, g.sh, g.nb, m);
+    const double rho = (double)density[sidx] * (g.leaf ? ldexp(1.0, -3 * g.leaf[4 * m + 3]) : 1.0); // mass
     double Tm = 0.0;
     double sum = 0.0;
     const bool emits = La > 0.0 && rho > 0.0 && u0 > 0.0;

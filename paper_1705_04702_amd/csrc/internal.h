@@ -46,12 +46,14 @@ hipError_t launch_table_readback(const double *src, double *dst, int64_t n_store
                                  int64_t ncell, hipStream_t stream);
 template <typename ImgT>
 hipError_t launch_image_scale(const ImgT *src, double *dst, int64_t n, double scale, hipStream_t stream);
-// Dust emission of a Cartesian grid (dust.hip).  Cells in natural order
-// m = ix + nx (iy + ny iz); tables and density in the bricked storage order.
+// Dust emission (dust.hip).  Cartesian cells in natural order
+// m = ix + nx (iy + ny iz), tables and density in the bricked storage order;
+// octree leaves in leaf order (storage order too).
 struct DustGrid {
     long long n_cells, n_store;
     int n_lambda;
     int n[3], bs[3], sh[3], nb[3];
+    const int *leaf; // octree: per leaf (origin x, y, z, level); NULL for Cartesian
 };
 struct DustTables {
     const double *t[4]; // absorption tables [n_lambda][n_store], summed

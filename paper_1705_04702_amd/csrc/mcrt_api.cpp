@@ -172,6 +172,7 @@ struct mcrt_dust {
     double *d_cdf = nullptr;     // [n_lambda][n_cells] running sums of the emission
     int *d_guide = nullptr;      // [n_lambda][K]
     double *d_T = nullptr;       // [n_cells] temperatures
+    int *d_leaf = nullptr;       // octree: [n_cells][4] leaf origin and level
     std::vector<double> L;       // emitted luminosity per wavelength
 };
 
@@ -649,6 +650,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         v.dust_cdf = dust->d_cdf;
         v.dust_guide = dust->d_guide;
         v.dust_K = dust->K;
+        v.dust_leaf = dust->d_leaf;
     }
     for (int c = 0; c < 3; ++c) v.src_pos[c] = (Real)s->source->pos[c];
     v.hR = (Real)s->source->hR;
@@ -779,6 +781,7 @@ void mcrt_dust_destroy(mcrt_dust *d)
     dev_free(d->d_cdf);
     dev_free(d->d_guide);
     dev_free(d->d_T);
+    dev_free(d->d_leaf);
     delete d;
 }
 
@@ -790,7 +793,6 @@ int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t 
     if (n < 1 || n > 4) return fail(MCRT_EINVAL, "dust_create: between 1 and 4 absorption results");
     const mcrt_medium *m = sim->medium;
     const mcrt_grid *g = m->grid;
-    if (g->type != kCartesian) return fail(MCRT_EINVAL, "dust_create: dust emission needs a Cartesian grid");
     if ((int)m->lambda_um.size() != m->n_lambda)
         return fail(MCRT_EINVAL, "dust_create: the medium was created without wavelengths");
     for (int i = 0; i < n; ++i)
@@ -835,12 +837,28 @@ int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t 
         dg.sh[a] = sim->sh[a];
         dg.nb[a] = sim->nb[a];
     }
+    int rc = MCRT_OK;
+    if (g->type == kOctree) {
+        std::vector<int32_t> node, geo;
+        std::string err;
+        const int depth = encode_octree((int64_t)g->first_child.size(), g->first_child.data(), nc, node, err);
+        if (depth < 0) rc = fail(MCRT_EINVAL, "dust_create: " + err);
+        if (!rc) {
+            leaf_geometry(node, depth, nc, geo);
+            rc = dev_alloc((void **)&d->d_leaf, geo.size() * sizeof(int32_t));
+            if (!rc) {
+                hipError_t e = hipMemcpy(d->d_leaf, geo.data(), geo.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+                if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("dust_create: ") + hipGetErrorString(e));
+            }
+        }
+        dg.leaf = d->d_leaf;
+    }
     DustTables tabs{};
     tabs.n = n;
     for (int i = 0; i < n; ++i) tabs.t[i] = absorbed[i]->d_table;
     const int blocks = dust_blocks(nc), tiles = dust_scan_tiles(nc);
     double *d_abs = nullptr, *d_part = nullptr, *d_lam = nullptr, *d_kw = nullptr, *d_tiles = nullptr;
-    int rc = dev_alloc((void **)&d->d_cdf, (size_t)nl * (size_t)nc * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d->d_cdf, (size_t)nl * (size_t)nc * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d->d_guide, (size_t)nl * (size_t)d->K * sizeof(int));
     if (!rc) rc = dev_alloc((void **)&d->d_T, (size_t)nc * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d_abs, (size_t)nc * sizeof(double));
@@ -922,8 +940,12 @@ int mcrt_run_dust_into(mcrt_sim *sim, const mcrt_dust *dust, uint64_t n_per_lamb
     if (!guard.owned) return fail(MCRT_EBUSY, "run_dust_into: the simulation is already running");
     if (count == 0) return MCRT_OK;
     HIP_TRY(hipSetDevice(sim->ctx->device));
-    if (sim->opt.precision == MCRT_FP32)
+    const bool oct = sim->medium->grid->type == kOctree;
+    if (sim->opt.precision == MCRT_FP32) {
+        if (oct) return run_impl<float, float, kOctree>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
         return run_impl<float, float, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
+    }
+    if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
     return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, dust);
 }
 

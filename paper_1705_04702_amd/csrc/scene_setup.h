@@ -241,6 +241,37 @@ inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_leve
     return true;
 }
 
+// Per leaf of an encoded octree (leaf order): its cube's origin on the
+// finest lattice (2^depth per axis) and its level, 4 ints per leaf.
+inline void leaf_geometry(const std::vector<int32_t> &node, int depth, int64_t n_leaves, std::vector<int32_t> &geo)
+{
+    geo.assign((size_t)n_leaves * 4, 0);
+    struct Item {
+        int32_t nd;
+        int level;
+        int32_t x, y, z; // origin in units of the node's own size
+    };
+    std::vector<Item> stack;
+    stack.push_back({0, 0, 0, 0, 0});
+    while (!stack.empty()) {
+        const Item it = stack.back();
+        stack.pop_back();
+        const int32_t v = node[(size_t)it.nd];
+        if (v < 0) {
+            const int64_t leaf = -(int64_t)v - 1;
+            const int sh = depth - it.level;
+            geo[(size_t)leaf * 4 + 0] = it.x << sh;
+            geo[(size_t)leaf * 4 + 1] = it.y << sh;
+            geo[(size_t)leaf * 4 + 2] = it.z << sh;
+            geo[(size_t)leaf * 4 + 3] = it.level;
+        } else {
+            for (int c = 0; c < 8; ++c)
+                stack.push_back({v + c, it.level + 1, 2 * it.x + (c & 1), 2 * it.y + ((c >> 1) & 1),
+                                 2 * it.z + ((c >> 2) & 1)});
+        }
+    }
+}
+
 // Brick shape for the Cartesian storage layout: 32 cells per brick (one
 // 128-byte line of FP32 densities); within a brick each axis's cell bits are
 // contiguous, in = sum_a (c_a mod 2^bs_a) << sh_a.  The first 8 cells of a

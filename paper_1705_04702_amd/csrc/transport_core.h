@@ -147,13 +147,14 @@ template <typename Real, typename ImgT, int G> struct View {
     int src_type;
     Real src_pos[3];
     Real hR, zs;
-    // dust emission (kDust, Cartesian): per wavelength the running sums of the
-    // cells' emission in natural cell order [n_lambda][n_cells], and a guide
+    // dust emission (kDust): per wavelength the running sums of the cells'
+    // emission in natural cell order (octree: leaf order) [n_lambda][n_cells], and a guide
     // of dust_K entries per wavelength: guide[k] = first cell whose running
     // sum exceeds k total / K
     const double *dust_cdf;
     const int *dust_guide;
     int dust_K;
+    const int *dust_leaf; // octree: per leaf (origin x, y, z on the 2^depth lattice, level)
     // instruments
     int n_ins;
     const InsDesc<Real> *ins;
@@ -1003,19 +1004,27 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.parked = false;
     ln.opt = v.optics[lam];
     Stream st = stream_of(v, ln);
-    // dust sources exist on Cartesian grids in the plain kernels only
-    constexpr bool kDustOn = G == kCartesian && !Sink::kLearn && !Sink::kHist;
+    // dust sources exist in the plain kernels only
+    constexpr bool kDustOn = !Sink::kLearn && !Sink::kHist;
     if (kDustOn && v.src_type == kDust) {
         // the emitting cell, then a uniform point inside it
         Real u0, u1, u2, u3;
         st.template pair<Real>(0, u0, u1);
         st.template pair<Real>(1, u2, u3);
         const long long m = dust_cell(v, lam, (double)u0);
-        const long long nxy = (long long)v.n[0] * v.n[1];
-        const int ix = (int)(m % v.n[0]), iy = (int)((m / v.n[0]) % v.n[1]), iz = (int)(m / nxy);
-        ln.r[0] = v.lo[0] + ((Real)ix + u1) * v.cs[0];
-        ln.r[1] = v.lo[1] + ((Real)iy + u2) * v.cs[1];
-        ln.r[2] = v.lo[2] + ((Real)iz + u3) * v.cs[2];
+        if constexpr (G == kCartesian) {
+            const long long nxy = (long long)v.n[0] * v.n[1];
+            const int ix = (int)(m % v.n[0]), iy = (int)((m / v.n[0]) % v.n[1]), iz = (int)(m / nxy);
+            ln.r[0] = v.lo[0] + ((Real)ix + u1) * v.cs[0];
+            ln.r[1] = v.lo[1] + ((Real)iy + u2) * v.cs[1];
+            ln.r[2] = v.lo[2] + ((Real)iz + u3) * v.cs[2];
+        } else {
+            const int *lf = v.dust_leaf + 4 * m;
+            const Real size = (Real)(1 << (v.depth - lf[3]));
+            ln.r[0] = v.lo[0] + ((Real)lf[0] + u1 * size) * v.cs[0];
+            ln.r[1] = v.lo[1] + ((Real)lf[1] + u2 * size) * v.cs[1];
+            ln.r[2] = v.lo[2] + ((Real)lf[2] + u3 * size) * v.cs[2];
+        }
     } else if (v.src_type == kExpDisk) {
         Real u0, u1, u2, u3;
         st.template pair<Real>(0, u0, u1);

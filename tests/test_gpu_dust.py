@@ -1,7 +1,8 @@
 """Dust emission phase on the GPU (Section 3.2, dust emission and
 self-absorption phases) against the oracle: cell temperatures and emitted
-luminosity per wavelength, FP64 parity of the dust packets' transport, the
-self-absorption cycles, FP32 energy balance, and the error cases."""
+luminosity per wavelength, FP64 parity of the dust packets' transport on
+Cartesian and octree grids, the self-absorption cycles, FP32 energy balance,
+and the error cases."""
 import numpy as np
 import pytest
 
@@ -88,14 +89,29 @@ def test_dust_fp32_energy_balance_and_flux():
     ctx.close()
 
 
+def test_dust_octree_fp64_parity():
+    """Clumpy torus (octree): leaf temperatures with the leaf volumes,
+    luminosities, and the dust packets' transport against the oracle."""
+    tor = scenes.torus(5, 4, 4, 16, n_clumps=20)
+    ctx = mcrt.Context(0)
+    sim = mcrt.Sim(ctx, tor, mcrt.FP64_VALIDATE)
+    st = sim.run(200, seed=3)
+    o = oracle.run(tor, 200, seed=3)
+    d = sim.dust([st], T0=30.0, beta=1.8)
+    T_o, em_o = oracle.dust_emission(tor, o["table"], T0=30.0, beta=1.8)
+    _close(d.temperature(), T_o, 1e-9)
+    assert np.allclose(d.luminosity(), em_o.sum(axis=0), rtol=1e-9, atol=0)
+    r = sim.run_dust(d, 200, seed=5)
+    od = oracle.run(oracle.dust_scene(tor, em_o), 200, seed=5)
+    _close(r.table(), od["table"])
+    for a, b in zip(r.images(), od["images"]):
+        _close(a, b)
+    sim.close()
+    ctx.close()
+
+
 def test_dust_errors():
     ctx = mcrt.Context(0)
-    tor = scenes.torus(5, 4, 2, 16, n_clumps=10)
-    so = mcrt.Sim(ctx, tor, mcrt.FP64_VALIDATE)
-    ro = so.run(20, seed=0)
-    with pytest.raises(mcrt.MCRTError):
-        so.dust([ro])                      # octree grid
-    so.close()
     sc = _disk()
     s1 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
     s2 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)

@@ -365,6 +365,16 @@ def _oracle_task(args):
     return r["stats"]["packets"], time.perf_counter() - t
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
     global _SC
     import numpy as np
@@ -395,7 +405,8 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
                       f"({packets} packets, {wall:.1f} s wall), one wavelength per task on "
                       f"{cores} processes",
             "single_core": {"value": single, "unit": "packets/s",
-                            "sample": f"packet ids [0, {c1}) of wavelengths {lams}, one process"}}
+                            "sample": f"packet ids [0, {c1}) of wavelengths {lams}, one process"},
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()}}
 
 
 def microbenchmarks():

@@ -8,15 +8,17 @@
 // with one atomic per wave; within a wave
 //   * dead lanes are refilled from the wave's chunk, ranked by mbcnt over the
 //     ballot of dead lanes (compaction of live packets);
-//   * all marching lanes advance their ray march one cell per iteration in
-//     lock step, whatever the march is for (propagation with deposits,
-//     interaction search or peel-off optical depth);
+//   * all marching lanes advance their ray march together, a fixed number of
+//     cells per iteration (the geometric steps first, then their density
+//     loads in flight together), whatever the march is for (propagation with
+//     deposits, interaction search or peel-off optical depth);
 //   * once at least `threshold` lanes have finished their march (ballot), the
 //     finished lanes process their event and start their next march.
 // Per-wavelength optics and the instrument frames are staged in LDS.  The
 // absorbed luminosity goes to the FP64 (wavelength, cell) table through
 // hardware FP64 atomic adds, the GPU form of the lock-free addition of
-// Section 5.2; peel-offs go to the images through hardware float atomics.
+// Section 5.2 (issued transposed through LDS, see DevSink); peel-offs go to
+// the images through hardware float atomics.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -334,7 +336,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
             continue;
         }
 
-        // march: every marching lane advances one cell per iteration
+        // march: every marching lane advances kK cells per iteration; the
+        // iteration's deposits go out after it
         for (;;) {
             if (ln.marching) march_batch<kK>(v, ln, ty, sink);
             sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, v.table, v.n_store, s_tc + wave * kTile,

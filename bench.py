@@ -114,7 +114,9 @@ def bench_batch(args):
                                   "log-uniform, tau 0.1-20, packets 1e5-1e7 each (total %d), 128^2 images, "
                                   "one persistent launch" % sum(npl), "models": 256},
            "kernel_ms_avg": sum(kms) / len(kms), "energy_balance_worst": worst,
-           "atomics_per_s": deposits / (sum(kms) / len(kms) / 1e3), "tuning": tuning}
+           "atomics_per_s": deposits / (sum(kms) / len(kms) / 1e3), "tuning": tuning,
+           "counters_per_packet": {f: sum(s[f] for s in sts) / max(sum(s["packets"] for s in sts), 1)
+                                   for f in ("events", "prop_cells", "locate_cells", "peel_cells", "peel_adds")}}
     for s in sims:
         s.close()
     print(json.dumps(out), flush=True)

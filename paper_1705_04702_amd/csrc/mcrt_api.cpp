@@ -998,11 +998,11 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     mcrt_sim *s0 = sims[0];
     hipStream_t st = s0->ctx->stream;
     // default chunk: large, since a wave drains its lanes whenever its next
-    // chunk belongs to another model -- total / (8 x waves), in 256 .. 16384
+    // chunk belongs to another model -- total / (16 x waves), in 256 .. 16384
     uint64_t total_packets = 0;
     for (int i = 0; i < n; ++i) total_packets += npl[i] * (uint64_t)sims[i]->medium->n_lambda;
     const int wpc0 = s0->opt.waves_per_cu > 0 ? s0->opt.waves_per_cu : 16;
-    uint64_t auto_chunk = total_packets / (32ull * (uint64_t)s0->ctx->n_cu * (uint64_t)wpc0);
+    uint64_t auto_chunk = total_packets / (16ull * (uint64_t)s0->ctx->n_cu * (uint64_t)wpc0);
     auto_chunk = auto_chunk < 256 ? 256 : (auto_chunk > 16384 ? 16384 : auto_chunk);
     const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? (uint64_t)s0->opt.chunk : auto_chunk);
     // Queue order: most expensive model first (longest-processing-time order,

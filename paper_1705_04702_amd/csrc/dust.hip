@@ -51,22 +51,23 @@ __device__ __forceinline__ double block_sum(double x, double *part)
     return r;
 }
 
+// In storage order (consecutive lanes read consecutive table elements); the
+// bricks' padding cells hold zeros and add nothing.
 __global__ void __launch_bounds__(kScanBlock)
 absorbed_kernel(DustGrid g, DustTables tabs, const float *density, double *absorbed, double *part_abs,
                 double *part_mass)
 {
     __shared__ double part[kScanBlock];
-    const long long m = (long long)blockIdx.x * kScanBlock + threadIdx.x;
+    const long long sidx = (long long)blockIdx.x * kScanBlock + threadIdx.x;
     double La = 0.0, rho = 0.0;
-    if (m < g.n_cells) {
-        const long long sidx = g.leaf ? m : brick_index(g.n, g.bs, g.sh, g.nb, m);
+    if (sidx < g.n_store) {
         for (int l = 0; l < g.n_lambda; ++l) {
             double t = tabs.t[0][(long long)l * g.n_store + sidx];
             for (int k = 1; k < tabs.n; ++k) t = t + tabs.t[k][(long long)l * g.n_store + sidx];
             La += t;
         }
-        rho = (double)density[sidx] * (g.leaf ? ldexp(1.0, -3 * g.leaf[4 * m + 3]) : 1.0); // mass
-        absorbed[m] = La;
+        rho = (double)density[sidx] * (g.leaf ? ldexp(1.0, -3 * g.leaf[4 * sidx + 3]) : 1.0); // mass
+        absorbed[sidx] = La;
     }
     const double sa = block_sum(La, part);
     const double sm = block_sum(rho, part);
@@ -90,33 +91,68 @@ emission_kernel(DustGrid g, const double *absorbed, const float *density, const 
 {
     const long long m = (long long)blockIdx.x * kScanBlock + threadIdx.x;
     if (m >= g.n_cells) return;
-    const double La = absorbed[m];
     const long long sidx = g.leaf ? m : brick_index(g.n, g.bs, g.sh, g.nb, m);
+    const double La = absorbed[sidx];
     const double rho = (double)density[sidx] * (g.leaf ? ldexp(1.0, -3 * g.leaf[4 * m + 3]) : 1.0); // mass
     double Tm = 0.0;
     double sum = 0.0;
     const bool emits = La > 0.0 && rho > 0.0 && u0 > 0.0;
     if (emits) {
         Tm = T0 * dm::exp(dm::log((La / rho) / u0) / (4.0 + beta));
-        for (int l = 0; l < g.n_lambda; ++l) sum += kw[l] * planck(lambda_um[l], Tm);
+        // each bin's shape kw B(T) goes to the output first, scaled below
+        for (int l = 0; l < g.n_lambda; ++l) {
+            const double w = kw[l] * planck(lambda_um[l], Tm);
+            emis[(long long)l * g.n_cells + m] = w;
+            sum += w;
+        }
     }
     T[m] = Tm;
     const bool ok = emits && sum > 0.0;
-    for (int l = 0; l < g.n_lambda; ++l)
-        emis[(long long)l * g.n_cells + m] = ok ? La * ((kw[l] * planck(lambda_um[l], Tm)) / sum) : 0.0;
+    for (int l = 0; l < g.n_lambda; ++l) {
+        double *e = emis + (long long)l * g.n_cells + m;
+        *e = ok ? La * (*e / sum) : 0.0;
+    }
 }
 
-// scan pass 1: per tile of one row, its sum
+// a tile of a row into LDS with coalesced loads (zeros past the end); each
+// thread then owns kScanItems consecutive elements (padded rows: no bank
+// conflicts on the per-thread reads)
+constexpr int kPad = kScanItems + 1;
+__device__ __forceinline__ void load_tile(const double *row, long long n, double *tile)
+{
+    const long long t0 = (long long)blockIdx.x * kScanTile;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int e = i * kScanBlock + threadIdx.x; // element within the tile
+        const long long g = t0 + e;
+        tile[(e / kScanItems) * kPad + e % kScanItems] = g < n ? row[g] : 0.0;
+    }
+    __syncthreads();
+}
+
+// scan pass 1: per tile of one row, its sum (thread sums of consecutive
+// elements, then the same fixed-shape scan as pass 3: its last element)
+__device__ __forceinline__ double thread_scan(double acc, double *part)
+{
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {
+        const double add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0.0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    return part[threadIdx.x]; // inclusive
+}
+
 __global__ void __launch_bounds__(kScanBlock) scan_tiles_kernel(const double *x, long long n, double *tile_sums)
 {
+    __shared__ double tile[kScanBlock * kPad];
     __shared__ double part[kScanBlock];
-    const double *row = x + (long long)blockIdx.y * n;
-    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+    load_tile(x + (long long)blockIdx.y * n, n, tile);
     double acc = 0.0;
-    for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) acc += row[base + i];
-    const double s = block_sum(acc, part);
-    if (threadIdx.x == 0) tile_sums[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    for (int i = 0; i < kScanItems; ++i) acc += tile[threadIdx.x * kPad + i];
+    const double incl = thread_scan(acc, part);
+    if (threadIdx.x == kScanBlock - 1) tile_sums[(long long)blockIdx.y * gridDim.x + blockIdx.x] = incl;
 }
 
 // scan pass 2: per row, exclusive running sums of its tiles (one thread a row)
@@ -133,30 +169,28 @@ __global__ void scan_offsets_kernel(double *tile_sums, int tiles, int rows)
 }
 
 // scan pass 3: inclusive running sums inside each tile, plus the tile offset
+// (the tile is staged through LDS both ways, so global accesses coalesce)
 __global__ void __launch_bounds__(kScanBlock) scan_apply_kernel(double *x, long long n, const double *offsets)
 {
+    __shared__ double tile[kScanBlock * kPad];
     __shared__ double part[kScanBlock];
     double *row = x + (long long)blockIdx.y * n;
-    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
-    double v[kScanItems];
+    load_tile(row, n, tile);
     double acc = 0.0;
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = base + i < n ? row[base + i] : 0.0;
-        acc += v[i];
-    }
+    for (int i = 0; i < kScanItems; ++i) acc += tile[threadIdx.x * kPad + i];
     // exclusive scan of the thread sums (Hillis-Steele over a fixed shape)
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int d = 1; d < kScanBlock; d <<= 1) {
-        const double add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0.0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-    }
-    double run = offsets[(long long)blockIdx.y * gridDim.x + blockIdx.x] + (part[threadIdx.x] - acc);
+    const double incl = thread_scan(acc, part);
+    double run = offsets[(long long)blockIdx.y * gridDim.x + blockIdx.x] + (incl - acc);
     for (int i = 0; i < kScanItems; ++i) {
-        run += v[i];
-        if (base + i < n) row[base + i] = run;
+        run += tile[threadIdx.x * kPad + i];
+        tile[threadIdx.x * kPad + i] = run;
+    }
+    __syncthreads();
+    const long long t0 = (long long)blockIdx.x * kScanTile;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int e = i * kScanBlock + threadIdx.x;
+        const long long g = t0 + e;
+        if (g < n) row[g] = tile[(e / kScanItems) * kPad + e % kScanItems];
     }
 }
 
@@ -180,12 +214,12 @@ __global__ void guide_kernel(const double *cdf, long long n, int K, int rows, in
 
 } // namespace
 
-int dust_blocks(long long n_cells) { return (int)((n_cells + kScanBlock - 1) / kScanBlock); }
+int dust_blocks(long long n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
 
 hipError_t launch_dust_absorbed(const DustGrid &g, const DustTables &tabs, const float *density, double *absorbed,
                                 double *part_abs, double *part_mass, hipStream_t st)
 {
-    hipLaunchKernelGGL(absorbed_kernel, dim3(dust_blocks(g.n_cells)), dim3(kScanBlock), 0, st, g, tabs, density,
+    hipLaunchKernelGGL(absorbed_kernel, dim3(dust_blocks(g.n_store)), dim3(kScanBlock), 0, st, g, tabs, density,
                        absorbed, part_abs, part_mass);
     return hipGetLastError();
 }

@@ -59,9 +59,10 @@ struct DustTables {
     const double *t[4]; // absorption tables [n_lambda][n_store], summed
     int n;
 };
-int dust_blocks(long long n_cells);    // blocks of the per-cell kernels (partial sums)
+int dust_blocks(long long n);          // blocks of the per-cell kernels over n cells (partial sums)
 int dust_scan_tiles(long long n);       // tiles per row of the scan
-// absorbed[m] = sum over wavelengths of the summed tables; part_* per block
+// absorbed[s] = sum over wavelengths of the summed tables, s in storage
+// order (n_store entries); part_* per block of dust_blocks(n_store)
 hipError_t launch_dust_absorbed(const DustGrid &g, const DustTables &tabs, const float *density, double *absorbed,
                                 double *part_abs, double *part_mass, hipStream_t st);
 // T[m] and emis[l][m] (see dust.hip)

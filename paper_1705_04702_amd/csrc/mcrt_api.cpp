@@ -856,12 +856,12 @@ int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t 
     DustTables tabs{};
     tabs.n = n;
     for (int i = 0; i < n; ++i) tabs.t[i] = absorbed[i]->d_table;
-    const int blocks = dust_blocks(nc), tiles = dust_scan_tiles(nc);
+    const int blocks = dust_blocks(sim->n_store), tiles = dust_scan_tiles(nc);
     double *d_abs = nullptr, *d_part = nullptr, *d_lam = nullptr, *d_kw = nullptr, *d_tiles = nullptr;
     if (!rc) rc = dev_alloc((void **)&d->d_cdf, (size_t)nl * (size_t)nc * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d->d_guide, (size_t)nl * (size_t)d->K * sizeof(int));
     if (!rc) rc = dev_alloc((void **)&d->d_T, (size_t)nc * sizeof(double));
-    if (!rc) rc = dev_alloc((void **)&d_abs, (size_t)nc * sizeof(double));
+    if (!rc) rc = dev_alloc((void **)&d_abs, (size_t)sim->n_store * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d_part, 2 * (size_t)blocks * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d_lam, (size_t)nl * sizeof(double));
     if (!rc) rc = dev_alloc((void **)&d_kw, (size_t)nl * sizeof(double));

@@ -81,8 +81,9 @@ def bench_batch(args):
     from paper_1705_04702_amd import mcrt, scenes
     models = scenes.batch(256, seed=4)
     ctx = mcrt.Context(0)
+    order = {"cost": mcrt.QUEUE_COST, "caller": mcrt.QUEUE_CALLER, "paired": mcrt.QUEUE_PAIRED}[args.queue_order]
     sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32, chunk=args.chunk or None, waves_per_cu=args.waves_per_cu or None,
-                     threshold=args.threshold or None) for m in models]
+                     threshold=args.threshold or None, queue_order=order) for m in models]
     npl = [m.n_packets for m in models]
     tuning = None
     if args.autotune:
@@ -112,7 +113,8 @@ def bench_batch(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch of 256 uniform-sphere / exponential-slab models, grids 16^3-128^3 "
                                   "log-uniform, tau 0.1-20, packets 1e5-1e7 each (total %d), 128^2 images, "
-                                  "one persistent launch" % sum(npl), "models": 256},
+                                  "one persistent launch" % sum(npl), "models": 256,
+                      "queue_order": args.queue_order},
            "kernel_ms_avg": sum(kms) / len(kms), "energy_balance_worst": worst,
            "atomics_per_s": deposits / (sum(kms) / len(kms) / 1e3), "tuning": tuning,
            "counters_per_packet": {f: sum(s[f] for s in sts) / max(sum(s["packets"] for s in sts), 1)
@@ -440,6 +442,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--threshold", type=int, default=0)
+    ap.add_argument("--queue-order", choices=("cost", "caller", "paired"), default="paired",
+                    help="batch: model order in the work queue")
     ap.add_argument("--brick", default="", help="log2 brick sizes, e.g. 1,0,4")
     ap.add_argument("--top-level", type=int, default=-1, help="octree top-table level (-1: the library's)")
     ap.add_argument("--curve", action="store_true",

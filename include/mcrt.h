@@ -80,12 +80,24 @@ typedef struct {
                               contribute nothing; default 40 */
     int32_t chunk;         /* packets per work-queue grab; 0 = default */
     int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = default */
-    int32_t threshold;     /* lanes that must finish a march before events run; 0 = default */
+    int32_t threshold;     /* lanes that must finish a march before events run; 0 = default
+                              (16; batches 24) */
     int32_t top_level;     /* octree top-table level; -1 = default */
     int32_t brick[3];      /* Cartesian storage bricks: log2 cells per axis, summing to 5
                               (32 cells per brick); {-1, -1, -1} = chosen from the cell
                               aspect ratio */
+    int32_t queue_order;   /* batches (the first simulation's options): the order of the
+                              models in the work queue, one of MCRT_QUEUE_*; default
+                              MCRT_QUEUE_PAIRED.  A model's random streams are keyed by its
+                              position in the caller's list, so no order changes a result,
+                              only the launch's tail (Section 7.4, Fig. 14) */
 } mcrt_options;
+
+/* Batch queue orders (Section 5.2 assigners; Section 7.4 load-balance lesson). */
+#define MCRT_QUEUE_COST 0   /* most expensive model first (longest processing time) */
+#define MCRT_QUEUE_CALLER 1 /* the caller's order (the sequential assigner's blocks) */
+#define MCRT_QUEUE_PAIRED 2 /* most and least expensive alternating (the suggested pairs;
+                               the default) */
 
 typedef struct {
     uint64_t packets;      /* packets launched */
@@ -180,7 +192,8 @@ int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint
  * results[i] (created with mcrt_result_create for sims[i]), all in ONE
  * persistent launch.  The position i in the batch is the fourth word of the
  * packets' Philox counters, so results equal per-model runs with model = i.
- * Queue tuning (chunk, threshold, waves per CU) comes from sims[0]'s options.
+ * Queue tuning (chunk, threshold, waves per CU) and the queue order come from
+ * sims[0]'s options.
  * Returns MCRT_ELIMIT (with valid results) if any packet hit its event cap. */
 int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_lambda, uint64_t seed,
                         mcrt_result *const *results);

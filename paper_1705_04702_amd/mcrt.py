@@ -61,7 +61,11 @@ class Options(ctypes.Structure):
         ("threshold", ctypes.c_int32),
         ("top_level", ctypes.c_int32),
         ("brick", ctypes.c_int32 * 3),
+        ("queue_order", ctypes.c_int32),
     ]
+
+
+QUEUE_COST, QUEUE_CALLER, QUEUE_PAIRED = 0, 1, 2
 
 
 STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
@@ -282,7 +286,10 @@ def sed_write_text(path, lambda_um, sed) -> None:
 def default_options(**kw) -> Options:
     o = Options()
     lib().mcrt_options_default(ctypes.byref(o))
+    names = {f[0] for f in Options._fields_}
     for k, val in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r}")
         if val is None:
             continue
         if k == "brick":

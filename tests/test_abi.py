@@ -38,7 +38,9 @@ def test_host_side_options_and_errors():
     from paper_1705_04702_amd import mcrt
     o = mcrt.default_options()
     assert o.precision == mcrt.FP32 and o.w_min == 1e-6 and o.event_cap == 10000
-    assert o.tau_peel_max == 40.0 and o.top_level == -1
+    assert o.tau_peel_max == 40.0 and o.top_level == -1 and o.queue_order == mcrt.QUEUE_PAIRED
+    with pytest.raises(TypeError):  # a misspelt option is an error, not a silent no-op
+        mcrt.default_options(treshold=8)
     L = mcrt.lib()
     h = ctypes.c_void_p()
     # a NULL context is rejected before any device call

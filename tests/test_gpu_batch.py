@@ -4,7 +4,8 @@ launch) and of the autotuner, through the C-ABI.
 Model i of a batch draws its packets' random numbers with counter word 3 =
 i, so each model must match the oracle run with model = i: FP64 validation
 to 1e-9 per cell and pixel, FP32 within the Monte Carlo noise.  Results may
-not depend on the queue tuning beyond the order of atomic additions.
+not depend on the queue tuning or the queue's model order beyond the order
+of atomic additions.
 """
 import os
 import sys
@@ -63,7 +64,9 @@ def test_batch_fp64_parity(ctx):
 
 
 @pytest.mark.parametrize("tune", [dict(chunk=16, threshold=4, waves_per_cu=4),
-                                  dict(chunk=512, threshold=48, waves_per_cu=16)])
+                                  dict(chunk=512, threshold=48, waves_per_cu=16),
+                                  dict(chunk=32, queue_order=mcrt.QUEUE_CALLER),
+                                  dict(chunk=32, queue_order=mcrt.QUEUE_COST)])
 def test_batch_tuning_invariance(ctx, tune):
     models, packets = batch_models(6, packet_div=5000)
     _, ref = run_batch(ctx, models, packets, mcrt.FP64_VALIDATE, seed=1, chunk=128)
@@ -97,7 +100,7 @@ def test_autotune_and_cache(ctx, tmp_path):
         t1 = mcrt.autotune(sims, [max(1, p // 4) for p in packets], seed=3, cache_path=cache)
         say(f"autotune: {t1}")
         assert not t1["from_cache"]
-        assert t1["chunk"] in (256, 512, 1024, 2048, 4096, 8192, 16384) and t1["threshold"] in (8, 16, 32, 48)
+        assert t1["chunk"] in (256, 512, 1024, 2048, 4096, 8192, 16384) and t1["threshold"] in (8, 16, 24, 32, 48)
         assert t1["waves_per_cu"] in (8, 12, 16) and t1["kernel_ms"] > 0
         t2 = mcrt.autotune(sims, [1] * len(sims), seed=3, cache_path=cache)
         assert t2["from_cache"] and (t2["chunk"], t2["threshold"], t2["waves_per_cu"]) == \
@@ -129,6 +132,9 @@ def test_batch_errors(ctx):
         with pytest.raises(mcrt.MCRTError) as ei:  # the same sim twice
             mcrt.batch_run_into([a, a], [ra, ra], [10, 10])
         assert ei.value.code == mcrt.EBUSY
+        with pytest.raises(mcrt.MCRTError) as ei:  # unknown queue order
+            mcrt.Sim(ctx, scenes.sphere(n=8), mcrt.FP32, queue_order=3)
+        assert ei.value.code == mcrt.EINVAL
     finally:
         for s in (a, b, t):
             s.close()

@@ -64,6 +64,27 @@ void dev_free(void *p)
     if (p) (void)hipFree(p);
 }
 
+// Owners released on every return path (HIP_TRY returns early).
+struct DevPtr {
+    void *p = nullptr;
+    DevPtr() = default;
+    DevPtr(const DevPtr &) = delete;
+    DevPtr &operator=(const DevPtr &) = delete;
+    ~DevPtr() { dev_free(p); }
+};
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventPair() = default;
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 bool finite_box(const double b[6])
 {
     for (int a = 0; a < 3; ++a)
@@ -704,22 +725,20 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
     if (grid < 1) grid = 1;
 
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+    HIP_TRY(hipEventRecord(ev.e0, st));
     hipError_t le;
     if constexpr (sizeof(Real) == 4 && G == kCartesian) le = launch_transport_f32c(a, grid, st);
     else if constexpr (sizeof(Real) == 4) le = launch_transport_f32o(a, grid, st);
     else if constexpr (G == kCartesian) le = launch_transport_f64c(a, grid, st);
     else le = launch_transport_f64o(a, grid, st);
     HIP_TRY(le);
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventRecord(ev.e1, st));
+    HIP_TRY(hipEventSynchronize(ev.e1));
     float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     r->kernel_ms = ms;
     unsigned long long stats[kNumStats];
     HIP_TRY(hipMemcpy(stats, r->d_stats, sizeof(stats), hipMemcpyDeviceToHost));
@@ -1086,13 +1105,13 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
         d.stats = res[i]->d_stats;
         chunk0 += (d.total + chunk - 1) / chunk;
     }
-    void *dmd = nullptr;
-    int rc = dev_alloc(&dmd, md.size() * sizeof(ModelDesc<Real, ImgT>));
+    DevPtr dmd;
+    int rc = dev_alloc(&dmd.p, md.size() * sizeof(ModelDesc<Real, ImgT>));
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(dmd, md.data(), md.size() * sizeof(ModelDesc<Real, ImgT>), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dmd.p, md.data(), md.size() * sizeof(ModelDesc<Real, ImgT>), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_zero(res[0]->d_counter, sizeof(unsigned long long), st));
     BatchArgs<Real, ImgT> a{};
-    a.models = (const ModelDesc<Real, ImgT> *)dmd;
+    a.models = (const ModelDesc<Real, ImgT> *)dmd.p;
     a.n_models = n;
     a.total_chunks = chunk0;
     a.chunk = chunk;
@@ -1103,21 +1122,18 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     if (waves > chunk0) waves = chunk0;
     int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
     if (grid < 1) grid = 1;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+    HIP_TRY(hipEventRecord(ev.e0, st));
     hipError_t le;
     if constexpr (sizeof(Real) == 4) le = launch_batch_f32(a, grid, st);
     else le = launch_batch_f64(a, grid, st);
     HIP_TRY(le);
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventRecord(ev.e1, st));
+    HIP_TRY(hipEventSynchronize(ev.e1));
     float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    dev_free(dmd);
+    HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     bool capped = false;
     for (int i = 0; i < n; ++i) {
         res[i]->kernel_ms = ms;

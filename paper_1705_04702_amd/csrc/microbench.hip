@@ -104,15 +104,15 @@ extern "C" int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_
         g_mb_err = "microbench: allocation failed";
         return MCRT_ENOMEM;
     }
-    (void)hipMemset(buf, 0, bytes);
+    hipError_t err = hipMemset(buf, 0, bytes);
     const int block = 256, grid = 256 * 32;
     const uint64_t threads = (uint64_t)block * grid;
     uint64_t iters = (n_ops + threads - 1) / threads;
     if (kind == 5) iters = (iters + 3) / 4 * 4;
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    for (int rep = 0; rep < 2; ++rep) { // first pass warms up
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) { // first pass warms up
         (void)hipEventRecord(e0, 0);
         switch (kind) {
         case 0:
@@ -147,13 +147,14 @@ extern "C" int mcrt_microbench(int device, int kind, uint64_t bytes, uint64_t n_
                                bytes / 8, iters);
             break;
         }
-        (void)hipEventRecord(e1, 0);
+        err = hipGetLastError();
+        if (err == hipSuccess) err = hipEventRecord(e1, 0);
     }
-    hipError_t err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(buf);
     if (buf2) (void)hipFree(buf2);
     if (err != hipSuccess) {

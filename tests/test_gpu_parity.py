@@ -301,6 +301,44 @@ def test_full_size_disk_in_the_bench_launch_configuration(ctx):
         sim.close()
 
 
+def test_full_size_torus(ctx):
+    """The clumpy torus at full size (2.24e6 leaves to depth 9, 1024^2
+    edge-on instrument): FP64 parity with the oracle on 3 of the 32
+    wavelengths for a packet-id range inside the full N; then bench.py's FP32
+    launch (ids [0, 1e6) of all 32 wavelengths): energy balance, packet
+    count, no capped packets, no octree walk stopped by its step guard, and
+    two half-ranges adding up to the whole."""
+    sc = scenes.torus()
+    N = 3_125_000
+    sub = type(sc)(**{**sc.__dict__})
+    keep = [0, 15, 31]
+    for f in ("lambdas", "kappa", "albedo", "hg_g", "lum"):
+        setattr(sub, f, np.ascontiguousarray(getattr(sc, f)[keep]))
+    sub.name = "torus_full_3l"
+    first, count = 1_234_567, 400
+    o = oracle.run(sub, N, seed=4, first_id=first, count=count)
+    g = gpu_run(ctx, sub, N, seed=4, first_id=first, count=count)
+    assert_fp64_parity(g, o)
+    B = 1_000_000
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    try:
+        say("full-size torus launch: ids [0, 1e6) x 32 wavelengths")
+        whole = sim.run(N, 0, 0, B)
+        halves = sim.new_result()
+        sim.run_into(halves, N, 0, 0, B // 2)
+        sim.run_into(halves, N, 0, B // 2, B - B // 2)
+        e = whole.energy()
+        assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5
+        st = whole.stats()
+        assert st["packets"] == B * sc.n_lambda and st["capped"] == 0 and st["guard"] == 0
+        np.testing.assert_allclose(halves.energy(), e, rtol=1e-6)
+        np.testing.assert_allclose(halves.table().sum(axis=0), whole.table().sum(axis=0), rtol=1e-5)
+        for r in (whole, halves):
+            r.close()
+    finally:
+        sim.close()
+
+
 def test_axis_aligned_instruments_fp64(ctx):
     """Peel-offs along the six grid axes (column maps, no march) next to an
     oblique one, on flat cells with sources inside and outside the grid and

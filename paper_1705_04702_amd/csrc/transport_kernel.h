@@ -366,9 +366,12 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     }
 }
 
-// FP32 production kernels: at most 168 VGPRs, three waves per SIMD.
+// FP32 production kernels: at most 168 VGPRs, three waves per SIMD; the
+// plain octree kernel, bound by the latency of its walk's dependent loads,
+// four waves per SIMD (128 VGPRs, a few registers spilled).
 template <int G, bool LEARN, bool HIST>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(G == kOctree && !LEARN && !HIST ? 4 : 3)))
 transport_kernel_f32(TransportArgs<float, float, G> a)
 {
     transport_body<float, float, G, LEARN, HIST>(a);

@@ -174,6 +174,16 @@ inline int encode_octree(int64_t n_nodes, const int32_t *first_child, int64_t n_
 // Returns false (with a message) if the blocks would not fit 32-bit indices.
 inline uint32_t walk_leaf(int level, int32_t val) { return (1u << 31) | ((uint32_t)level << 27) | (uint32_t)(-val - 1); }
 
+// Position of a top-level cube in the top table: 4 x 4 x 4 tiles (the
+// device's top_index), linear below level 2.
+inline int top_index_host(int x, int y, int z, int top_level)
+{
+    if (top_level < 2) return (((z << top_level) + y) << top_level) + x;
+    const int tl = top_level - 2;
+    const int tile = ((((z >> 2) << tl) + (y >> 2)) << tl) + (x >> 2);
+    return (tile << 6) + ((z & 3) << 4) + ((y & 3) << 2) + (x & 3);
+}
+
 inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_level, std::vector<int32_t> &top,
                        std::vector<int32_t> &blocks, std::string &err)
 {
@@ -227,7 +237,7 @@ inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_leve
                     if (block_of[(size_t)nd] < 0) block_of[(size_t)nd] = (int32_t)new_block(nd, level);
                     e = (uint32_t)block_of[(size_t)nd];
                 }
-                top[((size_t)bz * T + by) * T + bx] = (int32_t)e;
+                top[(size_t)top_index_host(bx, by, bz, top_level)] = (int32_t)e;
             }
     (void)depth;
     for (size_t w = 0; w < work.size(); ++w) {

@@ -232,6 +232,17 @@ template <typename Real> MCRT_HD Real rmax(Real a, Real b) { return a > b ? a : 
 // Storage position of Cartesian cell (ix, iy, iz): bricks of 32 cells shaped
 // to the cells' aspect ratio, so that successive cells of a ray tend to share
 // cache lines of the density and table arrays.
+// Octree top table: the cubes of the top level in tiles of 4 x 4 x 4 (256
+// bytes, each half one 128-byte line), so that the consecutive cubes of a
+// ray in any direction tend to share lines; linear below level 2.
+MCRT_HD int top_index(int x, int y, int z, int top_level)
+{
+    if (top_level < 2) return (((z << top_level) + y) << top_level) + x;
+    const int tl = top_level - 2;
+    const int tile = ((((z >> 2) << tl) + (y >> 2)) << tl) + (x >> 2);
+    return (tile << 6) + ((z & 3) << 4) + ((y & 3) << 2) + (x & 3);
+}
+
 template <typename Real, typename ImgT, int G>
 MCRT_HD int store_index(const View<Real, ImgT, G> &v, int ix, int iy, int iz)
 {
@@ -432,8 +443,7 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
         // locate the leaf holding lattice point ci: dense top table, then one
         // load per two levels (blocks of 4 x 4 x 4 sub-cubes)
         const int sh = v.depth - v.top_level;
-        const int T = 1 << v.top_level;
-        uint32_t e = (uint32_t)v.top[((ln.c2 >> sh) * T + (ln.c1 >> sh)) * T + (ln.c0 >> sh)];
+        uint32_t e = (uint32_t)v.top[top_index(ln.c0 >> sh, ln.c1 >> sh, ln.c2 >> sh, v.top_level)];
         int lv = v.top_level;
         while (!(e >> 31)) {
             const int s = v.depth - 1 - lv;

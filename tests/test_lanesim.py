@@ -48,7 +48,7 @@ def test_lane_logic_matches_oracle_fp64(name):
     assert l["stats"]["guard"] == 0
 
 
-@pytest.mark.parametrize("top_level", [0, 2, 5])
+@pytest.mark.parametrize("top_level", [0, 1, 2, 3, 5])
 def test_octree_top_table_levels(top_level):
     sc = scenes.torus(5, 4, 2, 16, n_clumps=20)
     o = oracle.run(sc, 150, seed=2)

@@ -459,9 +459,8 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             o[a] = cidx(ln, a) & ~(size - 1);
-            if (ln.d[a] > Real(0)) tn[a] = plane_t(v, ln, a, o[a] + size);
-            else if (ln.d[a] < Real(0)) tn[a] = plane_t(v, ln, a, o[a]);
-            else tn[a] = Prec<Real>::inf();
+            const Real t = plane_t(v, ln, a, ln.d[a] > Real(0) ? o[a] + size : o[a]);
+            tn[a] = ln.d[a] != Real(0) ? t : Prec<Real>::inf();
         }
         Real tmin = tn[0];
         int am = 0;
@@ -479,11 +478,15 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
         // lanes of a wave step different axes)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int q = ln.d[a] > Real(0) ? o[a] + size : o[a] - 1;
+            const int hi = o[a] + size - 1;
+            const int q = ln.d[a] > Real(0) ? hi + 1 : o[a] - 1;
             const Real p = ln.r[a] + te * ln.d[a];
-            const Real qf = floor(Prec<Real>::over_k(p - v.lo[a], v.cs[a], v.ics[a]));
-            const int qi = qf < Real(o[a]) ? o[a] : (qf > Real(o[a] + size - 1) ? o[a] + size - 1 : (int)qf);
-            exits = exits || (a == am && (q < 0 || q >= v.n[a]));
+            // truncation, then the clamp into [o, hi]: the same as floor
+            // then the clamp, since o >= 0 (p stays within the leaf up to
+            // rounding, so the conversion never overflows)
+            const int t = (int)Prec<Real>::over_k(p - v.lo[a], v.cs[a], v.ics[a]);
+            const int qi = t < o[a] ? o[a] : (t > hi ? hi : t);
+            exits = exits || (a == am && (unsigned)q >= (unsigned)v.n[a]);
             cidx(ln, a) = a == am ? q : qi;
         }
         if (++ln.steps >= v.octree_guard) {

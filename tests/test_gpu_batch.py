@@ -78,6 +78,25 @@ def test_batch_tuning_invariance(ctx, tune):
         np.testing.assert_allclose(a["energy"], b["energy"], rtol=1e-12)
 
 
+def test_batch_queue_orders_odd_count(ctx):
+    """Seven models (an odd count: the paired order ends on the middle model)
+    in every queue order give the same FP64 results, and match the oracle."""
+    models, packets = batch_models(5, packet_div=5000)
+    outs = {}
+    for order in (mcrt.QUEUE_COST, mcrt.QUEUE_CALLER, mcrt.QUEUE_PAIRED):
+        rc, outs[order] = run_batch(ctx, models, packets, mcrt.FP64_VALIDATE, seed=9, chunk=48,
+                                    queue_order=order)
+        assert rc == mcrt.OK
+    ref = outs[mcrt.QUEUE_CALLER]
+    for order in (mcrt.QUEUE_COST, mcrt.QUEUE_PAIRED):
+        for a, b in zip(outs[order], ref):
+            np.testing.assert_allclose(a["table"], b["table"], rtol=1e-12, atol=0)
+            for x, y in zip(a["images"], b["images"]):
+                np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+    for i, (sc, n, g) in enumerate(zip(models, packets, ref)):
+        assert_fp64_parity(g, oracle.run(sc, n, seed=9, model=i))
+
+
 def test_batch_fp32_energy_and_totals(ctx):
     models, packets = batch_models(8, packet_div=2000, extra=False)
     rc, out = run_batch(ctx, models, packets, mcrt.FP32, seed=2)

@@ -229,6 +229,20 @@ template <> struct Prec<double> {
 
 template <typename Real> MCRT_HD Real rmax(Real a, Real b) { return a > b ? a : b; }
 
+// Element i of a device buffer named by a view (a device allocation, never
+// LDS: the optics and instrument tables, which the kernels may stage in LDS,
+// do not go through here).  Saying so keeps the load a global one where the
+// view itself was read from memory (the batched kernel), which the compiler
+// would otherwise issue as a flat load.
+template <typename T> MCRT_HD T gload(const T *p, long long i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+#else
+    return p[i];
+#endif
+}
+
 // Storage position of Cartesian cell (ix, iy, iz): bricks of 32 cells shaped
 // to the cells' aspect ratio, so that successive cells of a ray tend to share
 // cache lines of the density and table arrays.
@@ -563,7 +577,7 @@ MCRT_HD void march_batch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty
     }
     float rho[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) rho[k] = v.density[ok[k] ? cell[k] : 0];
+    for (int k = 0; k < K; ++k) rho[k] = gload(v.density, ok[k] ? cell[k] : 0);
     bool stop = false;
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -657,7 +671,7 @@ MCRT_HD Real column_tau(const View<Real, ImgT, G> &v, const Lane<Real> &ln, cons
 {
     const Real tn = A == 0 ? ln.tn0 : (A == 1 ? ln.tn1 : ln.tn2);
     const int cell = store_index(v, ln.c0, ln.c1, ln.c2);
-    return ln.opt.kappa * ((Real)v.density[cell] * (tn - ln.t) + col[cell]);
+    return ln.opt.kappa * ((Real)gload(v.density, cell) * (tn - ln.t) + gload(col, cell));
 }
 
 template <typename Real, typename ImgT, int G>
@@ -1015,7 +1029,7 @@ MCRT_HD void launch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, uin
     ln.flux = Real(0);
     ln.emis_dir = false;
     ln.parked = false;
-    ln.opt = v.optics[lam];
+    ln.opt = v.optics[lam]; // (LDS or device memory: a generic load)
     Stream st = stream_of(v, ln);
     // dust sources exist in the plain kernels only
     constexpr bool kDustOn = !Sink::kLearn && !Sink::kHist;

@@ -413,7 +413,8 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
 // switches to a chunk of another model (tallies are flushed at the switch).
 // The model index is the fourth word of every packet's Philox counter.
 template <typename Real, typename ImgT>
-__device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a)
+__device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
+                                           const ModelDesc<Real, ImgT> *__restrict__ models)
 {
     // one deposit slot per segment: the batch's small tables stay in the L2,
     // where holding runs does not pay for its extra issue
@@ -438,11 +439,16 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a)
     Tally ty = {};
     int cur_model = -1, pend_model = -1;
     // The current model's view is read through a constant-address-space
-    // pointer: its fields become scalar loads the compiler may repeat instead
-    // of holding ~60 values in registers across the event loop.
+    // pointer formed from a wave-uniform model index at every use: its fields
+    // become scalar loads the compiler may repeat instead of holding ~60
+    // values in registers across the event loop (a pointer carried across
+    // the queue loop is not provably uniform, and its loads go to the vector
+    // memory path).
     typedef const View<Real, ImgT, 0> __attribute__((address_space(4))) CView;
-    CView *vc = (CView *)&a.models[0].view;
-    auto V = [&]() -> const View<Real, ImgT, 0> & { return *(const View<Real, ImgT, 0> *)vc; };
+    auto V = [&]() -> const View<Real, ImgT, 0> & {
+        const int m = __builtin_amdgcn_readfirstlane(cur_model < 0 ? 0 : cur_model);
+        return models[m].view;
+    };
     uint64_t count = 1, first_id = 0;
     uint64_t cur = 0, end = 0, pend_cur = 0, pend_end = 0;
     bool exhausted = false;
@@ -478,7 +484,6 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a)
                         flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
                     cur_model = pend_model;
                     const ModelDesc<Real, ImgT> &m = a.models[cur_model];
-                    vc = (CView *)&a.models[cur_model].view;
                     count = m.count;
                     first_id = m.first_id;
                 }
@@ -518,24 +523,24 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a)
 // FP32: at most 168 VGPRs, three waves per SIMD, as the single-model kernels.
 template <typename ImgT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-batch_transport_kernel_f32(BatchArgs<float, ImgT> a)
+batch_transport_kernel_f32(BatchArgs<float, ImgT> a, const ModelDesc<float, ImgT> *__restrict__ models)
 {
-    batch_body<float, ImgT>(a);
+    batch_body<float, ImgT>(a, models);
 }
 
 template <typename ImgT>
-__global__ void __launch_bounds__(kBlock) batch_transport_kernel_f64(BatchArgs<double, ImgT> a)
+__global__ void __launch_bounds__(kBlock) batch_transport_kernel_f64(BatchArgs<double, ImgT> a, const ModelDesc<double, ImgT> *__restrict__ models)
 {
-    batch_body<double, ImgT>(a);
+    batch_body<double, ImgT>(a, models);
 }
 
 template <typename Real, typename ImgT>
 hipError_t launch_batch_impl(const BatchArgs<Real, ImgT> &a, int grid, hipStream_t stream)
 {
     if constexpr (sizeof(Real) == 4)
-        hipLaunchKernelGGL(batch_transport_kernel_f32<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(batch_transport_kernel_f32<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a, a.models);
     else
-        hipLaunchKernelGGL(batch_transport_kernel_f64<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(batch_transport_kernel_f64<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a, a.models);
     return hipGetLastError();
 }
 

@@ -520,9 +520,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
     if (cur_model >= 0) flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
 }
 
-// FP32: at most 168 VGPRs, three waves per SIMD, as the single-model kernels.
+// FP32: four waves per SIMD (128 VGPRs, a few registers spilled): the
+// event-heavy batch gains more from the extra wave than the spills cost.
 template <typename ImgT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 batch_transport_kernel_f32(BatchArgs<float, ImgT> a, const ModelDesc<float, ImgT> *__restrict__ models)
 {
     batch_body<float, ImgT>(a, models);

@@ -474,8 +474,8 @@ def main():
         print(json.dumps({"copy_bytes": n * 4, "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is documented, not built)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(how the path would shard is documented, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -191,3 +191,21 @@ def init_params(seed=0, scale=1.0):
         else:
             p[name] = np.zeros(shape)
     return pack(p)
+
+
+def adam_step(theta, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One step of Adam (Kingma and Ba, ICLR 2015, Algorithm 1) in FP64.
+
+    The moment estimates are exponential averages of the gradient and of its
+    square; dividing them by 1 - beta^t removes the bias of their zero start;
+    the parameters move by lr times the corrected first moment over the
+    square root of the corrected second moment plus eps.  t >= 1 is the step
+    number.  Returns the new (theta, m, v).
+    """
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    theta = np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, m, v

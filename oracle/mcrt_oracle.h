@@ -47,7 +47,8 @@ typedef struct {
     const int32_t *ins_npix;    /* [n_ins][2]: nx, ny */
     double w_min;               /* termination fraction of the launch luminosity */
     int64_t event_cap;          /* maximum scattering events per packet */
-    double tau_peel_max;        /* peel-offs with optical depth >= this are dropped */
+    double tau_peel_max;        /* +inf: every peel-off counts (the definition); a finite value
+                                   drops peel-offs whose optical depth reaches it */
     /* learned direction proposal (NULL mlp = plain sampling) */
     const double *mlp;          /* 7400 parameters, weights bfloat16-representable */
     double alpha;               /* weight of the physical component */

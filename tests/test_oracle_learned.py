@@ -6,7 +6,12 @@
   sampling with the inverse-CDF cosine, tail behaviour;
 * the proposal mixture integrates to 1 (quadrature over the sphere) and the
   weights p_phys/q have expectation 1 under q (sampling);
-* bfloat16 rounding: nearest-even on exact halfway cases, idempotent.
+* bfloat16 rounding: nearest-even on exact halfway cases, idempotent;
+* the FP64 Adam step: against torch.optim.Adam (an independent
+  implementation, run on the CPU in float64) over several steps and
+  hyperparameters, and against its closed forms (the first step and every
+  step under a constant gradient move each parameter by lr g / (|g| + eps),
+  because the bias correction makes both moment estimates exact there).
 """
 import math
 
@@ -166,3 +171,44 @@ def test_histories_bookkeeping():
     assert tot.sum() == pytest.approx(r["images"][0].sum(), rel=1e-12)
     # luminosity after an event shrinks by at most the albedo
     assert np.all(L_e[:, 1:][rec[:, 1:]] <= L_e[:, :-1][rec[:, 1:]] * (1 + 1e-12))
+
+
+ADAM_CASES = [dict(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8),
+              dict(lr=1e-2, beta1=0.8, beta2=0.99, eps=1e-3),
+              dict(lr=3e-4, beta1=0.0, beta2=0.5, eps=1e-6)]
+
+
+@pytest.mark.parametrize("hp", ADAM_CASES)
+def test_adam_matches_torch(hp):
+    import torch
+    rng = np.random.default_rng(5)
+    theta0 = rng.normal(size=257)
+    grads = [rng.normal(size=257) * 10.0 ** rng.uniform(-4, 1, size=257) for _ in range(7)]
+    grads[3][:20] = 0.0
+    p = torch.nn.Parameter(torch.tensor(theta0, dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=hp["lr"], betas=(hp["beta1"], hp["beta2"]), eps=hp["eps"])
+    th, m, v = theta0.copy(), np.zeros(257), np.zeros(257)
+    for t, g in enumerate(grads, start=1):
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        th, m, v = L.adam_step(th, m, v, g, t, **hp)
+        assert np.allclose(th, p.detach().numpy(), rtol=1e-14, atol=1e-16)
+        st = opt.state[p]
+        # the moments differ by rounding order only (torch interpolates)
+        assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-12, atol=1e-15 * np.abs(m).max())
+        assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-12, atol=1e-15 * np.abs(v).max())
+
+
+@pytest.mark.parametrize("hp", ADAM_CASES)
+def test_adam_closed_forms(hp):
+    rng = np.random.default_rng(6)
+    theta0 = rng.normal(size=64)
+    g = rng.normal(size=64) * 10.0 ** rng.uniform(-3, 1, size=64)
+    step = hp["lr"] * g / (np.abs(g) + hp["eps"])
+    th, m, v = theta0, np.zeros(64), np.zeros(64)
+    for t in range(1, 6):
+        th, m, v = L.adam_step(th, m, v, g, t, **hp)
+        assert np.allclose(th, theta0 - t * step, rtol=1e-12, atol=1e-15)
+    # a zero gradient from a zero state leaves the parameters where they are
+    th0, _, _ = L.adam_step(theta0, np.zeros(64), np.zeros(64), np.zeros(64), 1, **hp)
+    assert np.array_equal(th0, theta0)

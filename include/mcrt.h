@@ -53,6 +53,8 @@ extern "C" {
 #define MCRT_EDEVICE (-3) /* HIP runtime error */
 #define MCRT_EBUSY (-4)   /* the simulation is already running */
 #define MCRT_ELIMIT (-5)  /* packets hit the event cap; results are valid, see stats.capped */
+#define MCRT_ENONFINITE (-6) /* packets whose luminosity became NaN or infinite were ended
+                                (see stats.nonfinite); the other packets' results are valid */
 
 #define MCRT_FP32 0           /* FP32 transport, FP64 table totals and energy sums */
 #define MCRT_FP64_VALIDATE 1  /* FP64 throughout, no contraction */
@@ -76,8 +78,12 @@ typedef struct {
                               w_min times its launch luminosity ("negligible part",
                               Section 3.2); default 1e-6 */
     int64_t event_cap;     /* maximum scattering events per packet; default 10000 */
-    double tau_peel_max;   /* peel-offs whose optical depth to the observer reaches this
-                              contribute nothing; default 40 */
+    double tau_peel_max;   /* default +infinity: every peel-off reaches its pixel, as the
+                              estimator defines it (Section 3.2, peel-off).  A finite value
+                              is an approximation the caller opts into: a peel-off march
+                              stops once its optical depth reaches tau_peel_max and that
+                              contribution is dropped, an error below exp(-tau_peel_max)
+                              of the contribution (40: 4e-18, below FP32 resolution) */
     int32_t chunk;         /* packets per work-queue grab; 0 = default */
     int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = default */
     int32_t threshold;     /* lanes that must finish a march before events run; 0 = default
@@ -109,14 +115,21 @@ typedef struct {
     uint64_t peel_dropped; /* peel-offs cut by tau_peel_max */
     uint64_t capped;       /* packets that hit the event cap */
     uint64_t guard;        /* octree marches stopped by the step guard (0 for valid trees) */
+    uint64_t nonfinite;    /* packets ended because their luminosity (or, with the learned
+                              proposal, their weight) became NaN or infinite; a finite
+                              scene gives 0 */
     double kernel_ms;      /* transport kernel time of the last run into this result */
 } mcrt_stats;
 
 /* Fills *opt with the defaults listed above. */
 void mcrt_options_default(mcrt_options *opt);
 
-/* Binds a device (HIP ordinal) and a stream (a hipStream_t such as torch's
- * current_stream().cuda_stream, or NULL for the default stream). */
+/* The execution resources every later call runs on (the role of the
+ * parallel engine's thread pool in Section 5.1.2 and 5.2.4, here one device
+ * and one stream): binds a device (HIP ordinal) and a stream (a hipStream_t
+ * such as torch's current_stream().cuda_stream, or NULL for the default
+ * stream; the caller keeps it alive).  Errors: MCRT_EINVAL (no such device,
+ * out NULL), MCRT_EDEVICE. */
 int mcrt_context_create(int device, void *hip_stream_or_null, mcrt_context **out);
 void mcrt_context_destroy(mcrt_context *ctx);
 
@@ -133,9 +146,14 @@ int mcrt_grid_create_octree(mcrt_context *ctx, const double box[6], int64_t n_no
                             const int32_t *first_child, mcrt_grid **out);
 void mcrt_grid_destroy(mcrt_grid *grid);
 
-/* Dust medium: density per cell (grid order), and per wavelength the
- * extinction coefficient kappa (per unit density and length), the albedo and
- * the Henyey-Greenstein asymmetry parameter g.  lambda_um may be NULL. */
+/* Dust medium (the dust system of Section 3.2 over the grid of the setup
+ * phase, with the wavelength grid of Section 7.2): density per cell (grid
+ * order; FP32, >= 0), and per wavelength the extinction coefficient kappa
+ * (per unit density and length, >= 0), the albedo (in [0, 1]) and the
+ * Henyey-Greenstein asymmetry parameter g (in (-1, 1)).  lambda_um (micron,
+ * increasing) may be NULL; the learned proposal, dust emission and the
+ * writing phase need it.  Host arrays, copied.  Errors: MCRT_EINVAL for
+ * values out of range or non-finite, MCRT_ENOMEM. */
 int mcrt_medium_create(mcrt_grid *grid, const float *density, int32_t n_lambda,
                        const double *lambda_um, const double *kappa, const double *albedo,
                        const double *g, mcrt_medium **out);
@@ -161,8 +179,13 @@ int mcrt_instrument_create(mcrt_context *ctx, double incl_deg, double azim_deg, 
                            const double fov[2], const int32_t npix[2], mcrt_instrument **out);
 void mcrt_instrument_destroy(mcrt_instrument *ins);
 
-/* Assembles a simulation and uploads the scene to the device.  opt may be
- * NULL for defaults.  The medium's and source's n_lambda must agree. */
+/* Assembles a simulation of the stellar emission phase (Section 3.2: the
+ * grid and dust system of the setup phase, the primary source, the
+ * instruments) and uploads the scene to the device; the device copy is
+ * read-only during runs (the per-run state lives in results).  opt may be
+ * NULL for defaults.  The medium's and source's n_lambda must agree; at
+ * most MCRT_MAX_INSTRUMENTS instruments.  Errors: MCRT_EINVAL, MCRT_ENOMEM,
+ * MCRT_EDEVICE. */
 int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
                     mcrt_instrument *const *ins, int32_t n_ins, const mcrt_options *opt,
                     mcrt_sim **out);
@@ -173,16 +196,25 @@ int mcrt_result_create(mcrt_sim *sim, mcrt_result **out);
 int mcrt_result_zero(mcrt_result *res);
 
 /* Runs packet ids [first_id, first_id + count) of every wavelength, each
- * packet carrying L / n_per_lambda, and ADDS their contributions to res.
- * Because absorbed luminosities add linearly (Section 5.2) and every packet
- * has its own counter-based random stream, running disjoint id ranges into
- * one result equals one run over their union (resume, sharding).  Returns
- * MCRT_ELIMIT (with valid results) if any packet hit the event cap. */
+ * packet carrying L / n_per_lambda (a fixed number of packets per
+ * wavelength, Section 3.2, stellar emission phase), and ADDS their
+ * contributions to res.  Because absorbed luminosities add linearly
+ * (Section 5.2.5) and every packet has its own counter-based random stream,
+ * running disjoint id ranges into one result equals one run over their union
+ * (resume, sharding).  Returns MCRT_ELIMIT (with valid results) if a packet
+ * of THIS launch hit the event cap, MCRT_ENONFINITE if a packet of this
+ * launch was ended for a non-finite luminosity (either is decided from the
+ * counts this launch added, not from earlier launches into res); also
+ * MCRT_EINVAL, MCRT_EBUSY, MCRT_EDEVICE. */
 int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
                   uint64_t seed, mcrt_result *res);
-/* Convenience: new result + run of all n_per_lambda packets per wavelength. */
+/* Convenience (Section 3.2, stellar emission phase: all n_per_lambda packets
+ * of every wavelength): new result + run; *out is set (and owned by the
+ * caller) on MCRT_OK, MCRT_ELIMIT and MCRT_ENONFINITE. */
 int mcrt_run(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t seed, mcrt_result **out);
-/* Convenience: new result + run of an id range. */
+/* Convenience: new result + run of an id range (one shard of the task
+ * parallel mode of Section 4.2, which splits the packets of every wavelength
+ * between processes); *out as for mcrt_run. */
 int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
                    uint64_t seed, mcrt_result **out);
 
@@ -318,8 +350,12 @@ int mcrt_proposal_eval(mcrt_proposal *p, const mcrt_histories *h, double *loss);
  * wavelength j (Section 5.2, ParallelTable element (i, j)); count >=
  * n_cells * n_lambda. */
 int mcrt_result_absorption(const mcrt_result *res, double *out, size_t count);
-/* Image of instrument ins, layout [lambda][y][x], flux units; count >=
- * n_lambda * ny * nx. */
+/* Image of instrument ins (its table of flux per pixel per wavelength, the
+ * instrument of Section 3.2 that emission and scattering events peel off
+ * onto; Section 5.2.6 for the wavelength-sliced data cube), layout
+ * [lambda][y][x], flux units (L phase exp(-tau) / (4 pi d^2) summed per
+ * pixel); FP64 copy of the FP32 production images; count >= n_lambda * ny *
+ * nx; host or device buffer. */
 int mcrt_result_image(const mcrt_result *res, int32_t ins, double *out, size_t count);
 /* SED of instrument ins: out[l] = total flux of wavelength slice l (the sum
  * of its pixels, flux units, reduced on the device in FP64 in a fixed order);
@@ -401,16 +437,27 @@ int mcrt_fits_cube_write_slices(const char *path, int64_t nx, int64_t ny, int32_
  * (17 significant digits). */
 int mcrt_sed_write_text(const char *path, int32_t n_lambda, const double *lambda_um, const double *sed);
 
-/* Energy sums (FP64): emitted = absorbed + escaped + truncated. */
+/* Energy sums (FP64) of the packets run into res: emitted (the launch
+ * luminosities), absorbed (the sum of the table, Section 3.2), escaped (the
+ * transmitted part of every propagation) and truncated (luminosity of
+ * packets ended once they kept only a negligible part of their launch
+ * luminosity, Section 3.2, or at the event cap); emitted = absorbed +
+ * escaped + truncated up to rounding (in expectation with the learned
+ * proposal).  Any pointer may be NULL. */
 int mcrt_result_energy(const mcrt_result *res, double *emitted, double *absorbed,
                        double *escaped, double *truncated);
+/* Counters of the packets run into res (mcrt_stats) and the kernel time of
+ * the last launch: the cells and pixels behind the per-packet work of
+ * Section 3.2 (propagation, forced interaction, peel-offs). */
 int mcrt_result_stats(const mcrt_result *res, mcrt_stats *stats);
 void mcrt_result_destroy(mcrt_result *res);
 
 /* Sizes of a simulation, for sizing result buffers. */
 int mcrt_sim_info(const mcrt_sim *sim, int64_t *n_cells, int32_t *n_lambda, int32_t *n_ins);
 
-/* Thread-local message describing the last failure of this thread. */
+/* Thread-local message describing the last failure of this thread (the
+ * boundary reports errors by code and message, never by exception; the
+ * client of Section 5.1.1 needs nothing else to use the library). */
 const char *mcrt_last_error(void);
 
 /* Memory-system microbenchmarks giving the transport kernel its roofline

@@ -8,7 +8,7 @@
 namespace mcrt {
 
 constexpr int kBlock = 256;    // threads per workgroup (4 waves)
-constexpr int kNumStats = 9;   // packets, events, prop, locate, peel cells, adds, dropped, capped, guard
+constexpr int kNumStats = 10;  // packets, events, prop, locate, peel cells, adds, dropped, capped, guard, nonfinite
 
 template <typename Real, typename ImgT, int G> struct View;
 template <typename Real> struct Optics;

@@ -74,7 +74,7 @@ typedef struct {
     double *table;   // [n_cells][n_lambda]
     double *images;  // concatenated [n_lambda][ny][nx] per instrument, flux
     double *energy;  // [4]
-    uint64_t *stats; // [9]
+    uint64_t *stats; // [10]
     double *hist;       // [packets][hist_events][14] or NULL
     double *hist_total; // [packets]
     int32_t hist_events;
@@ -227,8 +227,8 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     o->energy[1] = ty.absorbed;
     o->energy[2] = ty.escaped;
     o->energy[3] = ty.truncated;
-    uint64_t st[9] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells, ty.peel_cells,
-                      ty.peel_adds, ty.peel_dropped, ty.capped, ty.guard};
+    uint64_t st[10] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells, ty.peel_cells,
+                       ty.peel_adds, ty.peel_dropped, ty.capped, ty.guard, ty.nonfinite};
     std::memcpy(o->stats, st, sizeof(st));
     for (size_t q = 0; q < hist.size(); ++q) o->hist[q] = (double)hist[q];
     for (size_t q = 0; q < hist_total.size(); ++q) o->hist_total[q] = (double)hist_total[q];

@@ -205,7 +205,28 @@ struct mcrt_result {
     unsigned long long *d_stats = nullptr;   // [kNumStats]
     unsigned long long *d_counter = nullptr; // queue position
     double kernel_ms = 0.0;
+    // the cumulative capped / non-finite counts after the last launch into
+    // this result, so that a launch reports only what it added itself
+    unsigned long long seen_capped = 0, seen_nonfinite = 0;
 };
+
+// Codes after which a launch's results are still there to use.
+static inline bool soft_code(int rc) { return rc == MCRT_ELIMIT || rc == MCRT_ENONFINITE; }
+
+// The return code of a launch into r from the stats it left (stats[7]
+// capped, stats[9] non-finite): MCRT_ENONFINITE or MCRT_ELIMIT when this
+// launch raised the count, else MCRT_OK.
+static int launch_outcome(mcrt_result *r, const unsigned long long *stats)
+{
+    const bool capped = stats[7] > r->seen_capped, nonfinite = stats[9] > r->seen_nonfinite;
+    r->seen_capped = stats[7];
+    r->seen_nonfinite = stats[9];
+    if (nonfinite)
+        return fail(MCRT_ENONFINITE, "packets whose luminosity became NaN or infinite were ended (see "
+                                     "stats.nonfinite); the other packets' results are valid");
+    if (capped) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
+    return MCRT_OK;
+}
 
 // Definitions of the functions declared extern "C" in mcrt.h (they keep C
 // linkage from that declaration).
@@ -218,7 +239,7 @@ void mcrt_options_default(mcrt_options *opt)
     opt->precision = MCRT_FP32;
     opt->w_min = 1e-6;
     opt->event_cap = 10000;
-    opt->tau_peel_max = 40.0;
+    opt->tau_peel_max = HUGE_VAL;
     opt->chunk = 0;
     opt->waves_per_cu = 0;
     opt->threshold = 0;
@@ -603,6 +624,7 @@ int mcrt_result_zero(mcrt_result *res)
     HIP_TRY(launch_fill_zero(res->d_stats, kNumStats * sizeof(unsigned long long), st));
     HIP_TRY(hipStreamSynchronize(st));
     res->kernel_ms = 0.0;
+    res->seen_capped = res->seen_nonfinite = 0;
     return MCRT_OK;
 }
 
@@ -742,8 +764,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     r->kernel_ms = ms;
     unsigned long long stats[kNumStats];
     HIP_TRY(hipMemcpy(stats, r->d_stats, sizeof(stats), hipMemcpyDeviceToHost));
-    if (stats[7] > 0) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
-    return MCRT_OK;
+    return launch_outcome(r, stats);
 }
 
 namespace {
@@ -996,14 +1017,14 @@ int mcrt_dust_self_absorption(mcrt_sim *sim, const mcrt_result *stellar, const m
         rc = mcrt_run_dust_into(sim, dust, n_per_lambda, 0, n_per_lambda, seed + (uint64_t)(k - 1), rk);
         mcrt_result_destroy(prev);
         prev = rk;
-        if (rc && rc != MCRT_ELIMIT) break;
+        if (rc && !soft_code(rc)) break;
         double L = 0.0;
         for (double x : dust->L) L += x;
         const bool converged = k > 1 && std::fabs(L - Lprev) <= tol * L;
         Lprev = L;
         if (converged) break;
     }
-    if (rc && rc != MCRT_ELIMIT) {
+    if (rc && !soft_code(rc)) {
         mcrt_dust_destroy(dust);
         mcrt_result_destroy(prev);
         return rc;
@@ -1134,14 +1155,18 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     HIP_TRY(hipEventSynchronize(ev.e1));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
-    bool capped = false;
+    int worst = MCRT_OK;
     for (int i = 0; i < n; ++i) {
         res[i]->kernel_ms = ms;
         unsigned long long stt[kNumStats];
         HIP_TRY(hipMemcpy(stt, res[i]->d_stats, sizeof(stt), hipMemcpyDeviceToHost));
-        if (stt[7] > 0) capped = true;
+        const int oc = launch_outcome(res[i], stt);
+        if (oc == MCRT_ENONFINITE || (oc == MCRT_ELIMIT && worst == MCRT_OK)) worst = oc;
     }
-    if (capped) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
+    if (worst == MCRT_ENONFINITE)
+        return fail(MCRT_ENONFINITE, "packets whose luminosity became NaN or infinite were ended (see "
+                                     "stats.nonfinite); the other packets' results are valid");
+    if (worst == MCRT_ELIMIT) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
     return MCRT_OK;
 }
 
@@ -1247,7 +1272,7 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         int rc;
         if (n == 1) rc = mcrt_run_into(sims[0], trial_packets[0], 0, trial_packets[0], seed, res[0]);
         else rc = mcrt_batch_run_into(sims, n, trial_packets, seed, res.data());
-        if (rc != MCRT_OK && rc != MCRT_ELIMIT) return rc;
+        if (rc != MCRT_OK && !soft_code(rc)) return rc;
         ms = res[0]->kernel_ms;
         return MCRT_OK;
     };
@@ -1311,7 +1336,7 @@ int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint
     int rc = mcrt_result_create(sim, &r);
     if (rc) return rc;
     rc = mcrt_run_into(sim, n_per_lambda, first_id, count, seed, r);
-    if (rc != MCRT_OK && rc != MCRT_ELIMIT) {
+    if (rc != MCRT_OK && !soft_code(rc)) {
         std::string msg = g_err;
         mcrt_result_destroy(r);
         g_err = msg;
@@ -1458,6 +1483,7 @@ int mcrt_result_stats(const mcrt_result *res, mcrt_stats *stats)
     stats->peel_dropped = s[6];
     stats->capped = s[7];
     stats->guard = s[8];
+    stats->nonfinite = s[9];
     stats->kernel_ms = res->kernel_ms;
     return MCRT_OK;
 }
@@ -1888,7 +1914,7 @@ int mcrt_proposal_collect(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_i
             run_rc = oct ? run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res, h)
                          : run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, h);
         }
-        if (run_rc != MCRT_OK && run_rc != MCRT_ELIMIT) rc = run_rc;
+        if (run_rc != MCRT_OK && !soft_code(run_rc)) rc = run_rc;
     }
     // compaction into training samples
     uint32_t *d_count = nullptr;

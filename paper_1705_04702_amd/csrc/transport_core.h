@@ -182,6 +182,7 @@ template <typename Real, typename ImgT, int G> struct View {
 struct Tally {
     double emitted, absorbed, escaped, truncated;
     uint32_t packets, events, prop_cells, locate_cells, peel_cells, peel_adds, peel_dropped, capped, guard;
+    uint32_t nonfinite; // packets ended because their luminosity became NaN or infinite
 };
 
 template <typename Real> struct Lane {
@@ -925,7 +926,18 @@ MCRT_HD void apply_proposal(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally 
     }
     Real q = v.alpha * pphys + (Real(1) - v.alpha) * qv;
     ln.parked = false;
-    ln.L = (emis ? ln.L0 : ln.L) * (pphys / q);
+    const Real Lin = emis ? ln.L0 : ln.L;
+    ln.L = Lin * (pphys / q);
+    // a network that outputs NaN or infinity (diverged parameters) gives a
+    // non-finite weight, and a non-finite direction always does: the packet
+    // ends, counted, before the direction is marched; its luminosity before
+    // the weight is truncated, as at the event cap
+    if (!__builtin_isfinite(ln.L)) {
+        ty.truncated += (double)Lin;
+        ty.nonfinite++;
+        end_packet<Sink>(v, ln);
+        return;
+    }
     ln.k[0] = kp[0];
     ln.k[1] = kp[1];
     ln.k[2] = kp[2];
@@ -1145,7 +1157,16 @@ MCRT_HD void finish_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &t
     }
     if (ln.mode == kProp) {
         const Real Epath = ln.E;
-        ty.escaped += (double)(ln.L * Epath);
+        // L * Epath is finite exactly when both factors are (Epath <= 1): a
+        // packet whose luminosity or transmission went NaN or infinite ends
+        // here, counted, before it feeds another tally
+        const Real esc = ln.L * Epath;
+        if (!__builtin_isfinite(esc)) {
+            ty.nonfinite++;
+            end_packet<Sink>(v, ln);
+            return;
+        }
+        ty.escaped += (double)esc;
         if (ln.nseg == 0 || ln.opt.albedo == Real(0) || ln.tau == Real(0)) {
             end_packet<Sink>(v, ln);
             return;

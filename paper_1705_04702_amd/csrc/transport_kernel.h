@@ -352,7 +352,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     double e2 = wave_sum(ty.escaped), e3 = wave_sum(ty.truncated);
     unsigned long long s[kNumStats] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells,
                                        ty.peel_cells, ty.peel_adds, ty.peel_dropped, ty.capped,
-                                       ty.guard};
+                                       ty.guard, ty.nonfinite};
 #pragma unroll
     for (int i = 0; i < kNumStats; ++i) s[i] = wave_sum_u64(s[i]);
     if (lane == 0) {
@@ -391,7 +391,7 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
     double e2 = wave_sum(ty.escaped), e3 = wave_sum(ty.truncated);
     unsigned long long s[kNumStats] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells,
                                        ty.peel_cells, ty.peel_adds, ty.peel_dropped, ty.capped,
-                                       ty.guard};
+                                       ty.guard, ty.nonfinite};
 #pragma unroll
     for (int i = 0; i < kNumStats; ++i) s[i] = wave_sum_u64(s[i]);
     if (lane == 0) {

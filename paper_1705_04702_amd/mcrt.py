@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # MCRT_LIBRARY may name another build of the same library (e.g. a tuning variant)
 LIB_PATH = os.environ.get("MCRT_LIBRARY") or os.path.join(HERE, "libmcrt.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ELIMIT = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ELIMIT, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 FP32, FP64_VALIDATE = 0, 1
 
 EXPORTS = [
@@ -69,7 +69,7 @@ QUEUE_COST, QUEUE_CALLER, QUEUE_PAIRED = 0, 1, 2
 
 
 STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
-               "peel_dropped", "capped", "guard"]
+               "peel_dropped", "capped", "guard", "nonfinite"]
 
 
 class Tuning(ctypes.Structure):
@@ -461,7 +461,7 @@ class Sim:
             count = n_per_lambda - first_id
         h = ctypes.c_void_p()
         _check(lib().mcrt_proposal_collect(self.h, int(n_per_lambda), int(first_id), int(count), int(seed),
-                                           int(max_events), result.h, ctypes.byref(h)), allow=(ELIMIT,))
+                                           int(max_events), result.h, ctypes.byref(h)), allow=(ELIMIT, ENONFINITE))
         return Histories(h, self.ctx)
 
     def set_tuning(self, chunk: int, waves_per_cu: int, threshold: int):
@@ -480,7 +480,7 @@ class Sim:
         if count is None:
             count = n_per_lambda - first_id
         return _check(lib().mcrt_run_into(self.h, int(n_per_lambda), int(first_id), int(count),
-                                          int(seed), result.h), allow=(ELIMIT,))
+                                          int(seed), result.h), allow=(ELIMIT, ENONFINITE))
 
     def run(self, n_per_lambda: int, seed: int = 0, first_id: int = 0,
             count: Optional[int] = None) -> Result:
@@ -503,7 +503,7 @@ class Sim:
         if count is None:
             count = n_per_lambda - first_id
         return _check(lib().mcrt_run_dust_into(self.h, dust.h, int(n_per_lambda), int(first_id), int(count),
-                                               int(seed), result.h), allow=(ELIMIT,))
+                                               int(seed), result.h), allow=(ELIMIT, ENONFINITE))
 
     def run_dust(self, dust: Dust, n_per_lambda: int, seed: int = 0) -> Result:
         res = self.new_result()
@@ -518,7 +518,7 @@ class Sim:
         d, r, k = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int32()
         _check(lib().mcrt_dust_self_absorption(self.h, stellar.h, ctypes.byref(p), int(n_per_lambda), int(seed),
                                                int(max_cycles), float(tol), ctypes.byref(d), ctypes.byref(r),
-                                               ctypes.byref(k)), allow=(ELIMIT,))
+                                               ctypes.byref(k)), allow=(ELIMIT, ENONFINITE))
         dust = Dust(self, d)
         self._dusts.add(dust)
         res = Result(self, r)
@@ -598,10 +598,17 @@ class Proposal:
         return loss.value, g
 
     def train(self, hist: "Histories", epochs: int = 2, batch: int = 16384, lr: float = 1e-3,
-              seed: int = 1) -> float:
+              seed: int = 1, beta1: Optional[float] = None, beta2: Optional[float] = None,
+              eps: Optional[float] = None) -> float:
         o = TrainOpts()
         lib().mcrt_train_opts_default(ctypes.byref(o))
         o.epochs, o.batch, o.lr, o.seed = int(epochs), int(batch), float(lr), int(seed)
+        if beta1 is not None:
+            o.beta1 = float(beta1)
+        if beta2 is not None:
+            o.beta2 = float(beta2)
+        if eps is not None:
+            o.eps = float(eps)
         loss = ctypes.c_double()
         _check(lib().mcrt_proposal_train(self.h, hist.h, ctypes.byref(o), ctypes.byref(loss)))
         return loss.value
@@ -671,7 +678,7 @@ def batch_run_into(sims: Sequence["Sim"], results: Sequence[Result], n_per_lambd
     n = len(sims)
     npl = (ctypes.c_uint64 * n)(*[int(x) for x in n_per_lambda])
     return _check(lib().mcrt_batch_run_into(_handles(sims), n, npl, int(seed), _handles(results)),
-                  allow=(ELIMIT,))
+                  allow=(ELIMIT, ENONFINITE))
 
 
 def autotune(sims: Sequence["Sim"], trial_packets: Sequence[int], seed: int = 0,

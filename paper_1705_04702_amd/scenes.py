@@ -58,7 +58,7 @@ class Scene:
     disk_zs: float = 0.0
     w_min: float = 1e-6
     event_cap: int = 10000
-    tau_peel_max: float = 40.0
+    tau_peel_max: float = math.inf                 # no peel-off is cut (the definition)
     name: str = ""
 
     @property

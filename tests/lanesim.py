@@ -37,7 +37,7 @@ class _Out(ctypes.Structure):
 
 
 STATS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", "peel_adds",
-         "peel_dropped", "capped", "guard"]
+         "peel_dropped", "capped", "guard", "nonfinite"]
 _SRC = {"point_iso": 0, "point_aniso": 1, "expdisk": 2}
 _lib = None
 
@@ -110,7 +110,7 @@ def run(sc, n_per_lambda, seed=0, first_id=0, count=None, precision=1, top_level
     nimg = sum(int(np.prod(x)) for x in shapes)
     images = np.zeros(max(1, nimg))
     energy = np.zeros(4)
-    stats = np.zeros(9, dtype=np.uint64)
+    stats = np.zeros(len(STATS), dtype=np.uint64)
     o = _Out(table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
              images.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
              energy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

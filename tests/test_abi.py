@@ -1,6 +1,7 @@
 """The C-ABI library loads on the host and exports every function that
 include/mcrt.h declares (no compute calls: there is no GPU here)."""
 import ctypes
+import math
 import os
 import re
 
@@ -38,7 +39,7 @@ def test_host_side_options_and_errors():
     from paper_1705_04702_amd import mcrt
     o = mcrt.default_options()
     assert o.precision == mcrt.FP32 and o.w_min == 1e-6 and o.event_cap == 10000
-    assert o.tau_peel_max == 40.0 and o.top_level == -1 and o.queue_order == mcrt.QUEUE_PAIRED
+    assert o.tau_peel_max == math.inf and o.top_level == -1 and o.queue_order == mcrt.QUEUE_PAIRED
     with pytest.raises(TypeError):  # a misspelt option is an error, not a silent no-op
         mcrt.default_options(treshold=8)
     L = mcrt.lib()

@@ -136,6 +136,26 @@ def test_learned_transport_fp64_parity(ctx, name):
     assert_fp64_parity(g, o)
 
 
+def test_learned_full_size_torus_fp64(ctx):
+    """The learned proposal on the full clumpy torus (2.24e6 leaves to depth
+    9, 1024^2 edge-on instrument, anisotropic source): FP64 validation per
+    cell and pixel on 3 of the 32 wavelengths for a packet-id range inside
+    the full run's 3.125e6 ids per wavelength."""
+    sc = scenes.torus()
+    sub = type(sc)(**{**sc.__dict__})
+    keep = [0, 15, 31]
+    for f in ("lambdas", "kappa", "albedo", "hg_g", "lum"):
+        setattr(sub, f, np.ascontiguousarray(getattr(sc, f)[keep]))
+    sub.name = "torus_full_3l"
+    N, first, count = 3_125_000, 1_234_567, 400
+    theta = _params(11, scale=1.5, bias=0.1)
+    say(f"learned fp64 full torus ids [{first}, +{count}) x 3 wavelengths")
+    g = _run(ctx, sub, N, mcrt.FP64_VALIDATE, 4, theta, first_id=first, count=count)
+    o = oracle.run(sub, N, seed=4, first_id=first, count=count, mlp=theta)
+    assert g["stats"]["packets"] == 3 * count
+    assert_fp64_parity(g, o)
+
+
 @pytest.mark.parametrize("name", ["torus", "disk"])
 def test_histories_fp64_match_oracle(ctx, name):
     make, N = LEARNED[name]
@@ -218,6 +238,55 @@ def test_training_lowers_the_loss(ctx):
     again.close()
     h.close()
     prop.close()
+    sim.close()
+
+
+@pytest.mark.parametrize("hp", [dict(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8),
+                                dict(lr=1e-2, beta1=0.8, beta2=0.99, eps=1e-4)])
+def test_adam_steps_match_fp64_reference(ctx, hp):
+    """k Adam steps of mcrt_proposal_train against the FP64 Adam step.
+
+    The histories hold exactly one training sample, so every minibatch of a
+    step is that sample drawn batch times and the step's gradient is the
+    sample's normalised gradient at the current parameters, which
+    mcrt_proposal_grad gives for the same parameters.  Each training call
+    makes one step; the Adam state persists across calls.  The FP64
+    reference tracks m and v from those gradients and takes each step from
+    the device's previous parameters."""
+    sc = scenes.sphere(n=8, tau=1.0, albedo=0.5, g=0.5, npix=16)
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    res = sim.new_result()
+    say(f"adam steps {hp}")
+    h = sim.collect(res, 1, seed=3, max_events=1)
+    assert h.n_samples == 1
+    X, KP, C = h.samples()
+    theta0 = _params(5, scale=1.0, bias=0.05)
+    prop = mcrt.Proposal(ctx, params=theta0)
+    probe = mcrt.Proposal(ctx, params=theta0)
+    m = np.zeros(L.N_PARAMS)
+    v = np.zeros(L.N_PARAMS)
+    prev = prop.params()
+    lr = hp["lr"]
+    for t in range(1, 6):
+        probe.set_params(prev)
+        _, g = probe.grad(X, KP, C)
+        assert np.count_nonzero(g) > 1000
+        prop.train(h, epochs=1, batch=64, seed=t, **hp)
+        cur = prop.params()
+        ref, m, v = L.adam_step(prev.astype(np.float64), m, v, g.astype(np.float64), t, **hp)
+        # FP32 moments and update, FP32 parameters; the minibatch gradient
+        # (64 copies of the sample, scaled by 1/64) differs from the single
+        # sample's by the rounding of its bf16 high + low parts
+        tol = 3e-5 * lr + 2.0 * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        err = np.abs(cur - ref)
+        step = np.abs(ref - prev)
+        say(f"adam t={t}: max err {err.max():.3e} (tol min {tol.min():.1e}), step median "
+            f"{np.median(step):.3e}")
+        assert np.all(err <= tol)
+        prev = cur
+    probe.close()
+    prop.close()
+    h.close()
     sim.close()
 
 

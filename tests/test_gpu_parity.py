@@ -93,14 +93,6 @@ def test_sphere_c1_fp64_full(ctx):
     assert_fp64_parity(g, o)
 
 
-def test_sphere_c1_fp32_statistical(ctx):
-    sc = scenes.sphere()
-    N = 100000
-    o = oracle.run(sc, N, seed=0, moments=True)
-    g = gpu_run(ctx, sc, N, seed=0, precision=mcrt.FP32)
-    assert_fp32_statistical(g, o, N)
-
-
 @pytest.mark.parametrize("make,N", [
     (lambda: scenes.disk((32, 32, 16), 8, 64), 600),
     (lambda: scenes.torus(6, 5, 4, 128, n_clumps=60), 400),

@@ -320,3 +320,18 @@ def test_moments_match_batch_spread():
     big = T > 0.2 * T.max()
     ratio = np.sqrt(np.maximum(var[big], 0)) / sd[big]
     assert 0.6 < np.median(ratio) < 1.6
+
+
+def test_threaded_id_ranges_equal_one_run():
+    """The test harness's threaded oracle (disjoint id ranges, summed) equals
+    one serial run, second moments included."""
+    import oracle_par
+    sc = scenes.disk((16, 16, 8), 3, 24)
+    a = oracle.run(sc, 900, seed=4, first_id=17, count=613, moments=True)
+    b = oracle_par.run(sc, 900, seed=4, first_id=17, count=613, moments=True, threads=5)
+    for k in ("table", "table_m2"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=0)
+    for x, y in zip(b["images"] + b["image_m2"], a["images"] + a["image_m2"]):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(b["energy"], a["energy"], rtol=1e-12)
+    assert b["stats"] == a["stats"]

@@ -9,8 +9,9 @@ threshold, the interaction segment, a bf16 activation of the network) takes
 another path.  The bar is the Monte Carlo one: on cells and pixels with at
 least 10 effective contributions (T^2 / sum of squared per-packet
 contributions), at most 0.5 % may differ from the oracle by more than 3
-sigma, sigma^2 = sum_p s_p^2 - T^2 / N from the oracle's per-packet second
-moments; result totals within 1e-4 (images) or 1e-5 (tables) relative plus
+sigma plus an FP32 arithmetic allowance of 1e-3 |T| (which only matters
+where sigma vanishes), sigma^2 = sum_p s_p^2 - T^2 / N from the oracle's
+per-packet second moments; result totals within 1e-4 (images) or 1e-5 (tables) relative plus
 3 sigma; energy balance 1e-5.  Every result's maximum, 99th-percentile and
 median relative error (over the selected entries) and its total's relative
 error are printed as a JSON line tagged [fp32-err] (and appended to the file
@@ -38,6 +39,14 @@ from test_gpu_parity import say
 pytestmark = pytest.mark.gpu
 
 NEFF_MIN = 10.0
+# FP32 arithmetic allowance, for entries whose Monte Carlo sigma vanishes (a
+# point source's emission peel-off adds the same value for every packet).
+# Such an entry differs from the oracle only by FP32 rounding: its optical
+# depth summed over n cells carries at most (n + 3) 2^-24 tau (about 8e-4 for
+# the torus's ~250-cell edge-on ray at tau ~ 50), and its k atomic additions
+# (a wave's 64 adds are combined first) at most k 2^-24 (2e-5 for 20000
+# packets).
+FP32_ALLOWANCE = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +74,10 @@ def _errors(name, a, T, m2, N, sum_tol):
     if sel.any():
         d = np.abs(a[sel] - T[sel])
         rel = d / np.abs(T[sel])
-        beyond = d > 3.0 * np.sqrt(var[sel]) + 1e-7 * np.abs(T[sel])
+        beyond = d > 3.0 * np.sqrt(var[sel]) + FP32_ALLOWANCE * np.abs(T[sel])
+        worst = np.argsort(-(d / (3.0 * np.sqrt(var[sel]) + FP32_ALLOWANCE * np.abs(T[sel]))))[:3]
+        rec["worst"] = [dict(rel=float(rel[w]), sigma_rel=float(np.sqrt(var[sel][w]) / abs(T[sel][w])),
+                             neff=float(neff[sel][w])) for w in worst]
         rec.update(frac_beyond_3sigma=float(beyond.mean()), max_rel_err=float(rel.max()),
                    p99_rel_err=float(np.quantile(rel, 0.99)), median_rel_err=float(np.median(rel)))
         assert beyond.mean() <= 0.005, (name, rec)

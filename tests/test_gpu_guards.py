@@ -93,8 +93,10 @@ def test_nonfinite_weights_fp32_match_capped_plain(ctx):
 
 
 def test_event_cap_code_describes_its_own_launch(ctx):
-    sc = scenes.sphere(n=8, tau=3.0, albedo=0.9, g=0.3)
-    sc.event_cap = 4
+    # a cap of 2 events and w_min = 0.3: about half the packets hit the cap
+    sc = scenes.sphere(n=8, tau=1.0, albedo=0.9, g=0.3)
+    sc.event_cap = 2
+    sc.w_min = 0.3
     # which ids hit the cap: one-packet oracle runs
     capped = [oracle.run(sc, 64, seed=2, first_id=i, count=1)["stats"]["capped"] for i in range(64)]
     hit = [i for i in range(64) if capped[i]]

@@ -2,8 +2,10 @@
 C-ABI.
 
 * FP64 validation mode: per cell and per pixel |gpu - oracle| <= 1e-9 |oracle|
-  and identical zero patterns; identical event and cell counters.  The only
-  allowed difference is the order of the atomic additions.
+  (plus 16 spacings of the subnormal range, 16 x 2^-1074, where relative
+  agreement is not representable) and identical zero patterns; identical
+  event and cell counters.  The only allowed differences are the order of
+  the atomic additions and of the factors of a product.
 * FP32 production mode: on cells and pixels with an effective number of
   contributions >= 10, at most 0.5 % may differ from the oracle by more than
   3 sigma (sigma from the oracle's per-packet second moments); global sums
@@ -22,6 +24,12 @@ from paper_1705_04702_amd import mcrt, scenes
 pytestmark = pytest.mark.gpu
 
 REL_FP64 = 1e-9
+# Below the smallest normal double (2^-1022) values are spaced 2^-1074 apart,
+# so relative agreement degrades there (a pixel of 1e-317 holds 7 significant
+# digits).  The two sides form a value with the same factors in different
+# orders, each rounding at most half a spacing: 16 spacings of absolute slack
+# cover that, and nothing above the subnormal range.
+ABS_SUBNORMAL = 16 * 2.0 ** -1074
 
 
 def say(msg):
@@ -49,9 +57,11 @@ def assert_fp64_parity(g, o, counters=True):
             (f"image{j}", x, y) for j, (x, y) in enumerate(zip(g["images"], o["images"]))]:
         assert np.array_equal(a == 0, b == 0), f"{name}: zero patterns differ"
         nz = b != 0
-        rel = np.abs(a[nz] - b[nz]) / np.abs(b[nz])
+        d = np.abs(a[nz] - b[nz])
+        rel = d / np.abs(b[nz])
         say(f"{name}: {nz.sum()} nonzero, max rel err {rel.max() if rel.size else 0:.3e}")
-        assert rel.size == 0 or rel.max() <= REL_FP64, f"{name}: max rel {rel.max()}"
+        bad = d > REL_FP64 * np.abs(b[nz]) + ABS_SUBNORMAL
+        assert not bad.any(), f"{name}: max rel {rel[bad].max()} at |oracle| {np.abs(b[nz][bad]).min():.3e}"
     # global FP64 sums: the summation order differs (bound ~ N eps)
     np.testing.assert_allclose(g["energy"], o["energy"], rtol=REL_FP64)
     if counters:

@@ -208,6 +208,22 @@ int mcrt_result_zero(mcrt_result *res);
  * MCRT_EINVAL, MCRT_EBUSY, MCRT_EDEVICE. */
 int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
                   uint64_t seed, mcrt_result *res);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): mcrt_run_into without
+ * any allocation, copy from the host or event creation in the call.  Same
+ * arguments, results, errors and return codes as mcrt_run_into (the same
+ * kernels).  The launch's scratch -- the work-queue counter and the
+ * per-wavelength optics staged for the launch -- lives in a fixed device
+ * array of 164096 bytes per GPU that the library holds until the process
+ * ends (its address is taken when the first context on that GPU is
+ * created) and that every call on that GPU shares: the call prepares it on
+ * the device, so nothing of an earlier call's contents leaks into a later
+ * one, but calls that overlap on one GPU (from several threads or streams)
+ * race on it and must not be made.  At most 4096 wavelengths (MCRT_EINVAL
+ * beyond).  The kernel is not timed (stats.kernel_ms reads 0).  The caller
+ * creates the sim and the result beforehand (those calls allocate). */
+int mcrt_run_into_noalloc(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count,
+                          uint64_t seed, mcrt_result *res);
 /* Convenience (Section 3.2, stellar emission phase: all n_per_lambda packets
  * of every wavelength): new result + run; *out is set (and owned by the
  * caller) on MCRT_OK, MCRT_ELIMIT and MCRT_ENONFINITE. */

@@ -32,6 +32,7 @@ UNITS = [
     ("proposal.hip", ["-x", "hip"]),
     ("microbench.hip", ["-x", "hip"]),
     ("dust.hip", ["-x", "hip", "-ffp-contract=off"]),
+    ("noalloc.hip", ["-x", "hip", "-ffp-contract=off"]),
     ("mcrt_api.cpp", []),
     ("output.cpp", []),
 ]

@@ -36,6 +36,21 @@ hipError_t launch_transport_f32o(const TransportArgs<float, float, 1> &a, int gr
 hipError_t launch_transport_f64c(const TransportArgs<double, double, 0> &a, int grid, hipStream_t stream);
 hipError_t launch_transport_f64o(const TransportArgs<double, double, 1> &a, int grid, hipStream_t stream);
 
+// Allocation-free runs (noalloc.hip): a file-scope device array per GPU
+// holds the queue counter (first kNoAllocHeader bytes) and the launch's
+// per-wavelength optics (at most kNoAllocMaxLambda).  setup takes the
+// array's device address for `device` (that device current) once; scratch
+// returns it (NULL before setup).  launch_noalloc_setup zeroes the counter and
+// writes the optics from the sim's device copies with L0 = lum / n_per_lambda.
+constexpr size_t kNoAllocHeader = 256;
+constexpr int kNoAllocMaxLambda = 4096;
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
+template <typename Real>
+hipError_t launch_noalloc_setup(void *scratch_dev, const Optics<Real> *optics_base, const double *lum, int n_lambda,
+                                uint64_t n_per_lambda, hipStream_t stream);
+
 // auxiliary kernels (aux_kernels.hip)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 // dst[(c - cell0) * n_lambda + l] = src[l * n_store + store(c)] for cells c in

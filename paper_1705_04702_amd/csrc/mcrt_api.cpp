@@ -154,6 +154,8 @@ struct mcrt_sim {
     int *d_node = nullptr;
     int *d_top = nullptr;
     void *d_optics = nullptr; // Optics<Real>[n_lambda], rewritten per run
+    void *d_optics_base = nullptr; // Optics<Real>[n_lambda] with L0 = 0 (allocation-free runs)
+    double *d_lum = nullptr;       // source luminosity per wavelength, FP64 (allocation-free runs)
     void *d_ins = nullptr;    // InsDesc<Real>[n_ins]
     void *d_col[kMaxIns] = {}; // column maps of axis-aligned instruments (Cartesian), Real[n_store]
     std::atomic<int> busy{0};
@@ -256,6 +258,10 @@ int mcrt_context_create(int device, void *stream, mcrt_context **out)
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(MCRT_EINVAL, "context_create: no such device");
     HIP_TRY(hipSetDevice(device));
+    // the device address of this device's allocation-free scratch, once
+    const hipError_t se = noalloc_scratch_setup(device);
+    if (se != hipSuccess)
+        return fail(MCRT_EDEVICE, std::string("context_create: scratch address: ") + hipGetErrorString(se));
     int ncu = 0;
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     auto *c = new mcrt_context;
@@ -432,6 +438,8 @@ static void sim_free_device(mcrt_sim *s)
     dev_free(s->d_node);
     dev_free(s->d_top);
     dev_free(s->d_optics);
+    dev_free(s->d_optics_base);
+    dev_free(s->d_lum);
     dev_free(s->d_ins);
     for (int j = 0; j < kMaxIns; ++j) {
         dev_free(s->d_col[j]);
@@ -441,6 +449,8 @@ static void sim_free_device(mcrt_sim *s)
     s->d_node = nullptr;
     s->d_top = nullptr;
     s->d_optics = nullptr;
+    s->d_optics_base = nullptr;
+    s->d_lum = nullptr;
     s->d_ins = nullptr;
 }
 
@@ -472,8 +482,23 @@ template <typename Real> static int upload_instruments(mcrt_sim *s)
     int rc = dev_alloc(&s->d_ins, d.size() * sizeof(InsDesc<Real>));
     if (rc) return rc;
     HIP_TRY(hipMemcpy(s->d_ins, d.data(), d.size() * sizeof(InsDesc<Real>), hipMemcpyHostToDevice));
-    rc = dev_alloc(&s->d_optics, (size_t)s->medium->n_lambda * sizeof(Optics<Real>));
-    return rc;
+    const int nl = s->medium->n_lambda;
+    rc = dev_alloc(&s->d_optics, (size_t)nl * sizeof(Optics<Real>));
+    // device copies the allocation-free run prepares its optics from
+    std::vector<Optics<Real>> base((size_t)nl);
+    for (int l = 0; l < nl; ++l) {
+        base[l].kappa = (Real)s->medium->kappa[l];
+        base[l].albedo = (Real)s->medium->albedo[l];
+        base[l].g = (Real)s->medium->g[l];
+        base[l].L0 = Real(0);
+        base[l].lamf = (Real)s->lamf[l];
+    }
+    if (!rc) rc = dev_alloc(&s->d_optics_base, (size_t)nl * sizeof(Optics<Real>));
+    if (!rc) rc = dev_alloc((void **)&s->d_lum, (size_t)nl * sizeof(double));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(s->d_optics_base, base.data(), base.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_lum, s->source->L.data(), (size_t)nl * sizeof(double), hipMemcpyHostToDevice));
+    return MCRT_OK;
 }
 
 int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source, mcrt_instrument *const *ins,
@@ -654,21 +679,30 @@ int mcrt_result_create(mcrt_sim *sim, mcrt_result **out)
 
 template <typename Real, typename ImgT, int G>
 static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
-                    mcrt_result *r, mcrt_histories *hist = nullptr, const mcrt_dust *dust = nullptr)
+                    mcrt_result *r, mcrt_histories *hist = nullptr, const mcrt_dust *dust = nullptr,
+                    void *scratch = nullptr)
 {
     const mcrt_medium *m = s->medium;
     const mcrt_grid *g = m->grid;
     hipStream_t st = s->ctx->stream;
-    std::vector<Optics<Real>> optics((size_t)m->n_lambda);
-    for (int l = 0; l < m->n_lambda; ++l) {
-        optics[l].kappa = (Real)m->kappa[l];
-        optics[l].albedo = (Real)m->albedo[l];
-        optics[l].g = (Real)m->g[l];
-        optics[l].L0 = (Real)((dust ? dust->L[l] : s->source->L[l]) / (double)n_per_lambda);
-        optics[l].lamf = (Real)s->lamf[l];
+    if (scratch) {
+        // allocation-free: counter and optics in the device's scratch array,
+        // prepared on the device (no host buffer, no copy from the host)
+        HIP_TRY(launch_noalloc_setup<Real>(scratch, (const Optics<Real> *)s->d_optics_base, s->d_lum, m->n_lambda,
+                                           n_per_lambda, st));
+    } else {
+        std::vector<Optics<Real>> optics((size_t)m->n_lambda);
+        for (int l = 0; l < m->n_lambda; ++l) {
+            optics[l].kappa = (Real)m->kappa[l];
+            optics[l].albedo = (Real)m->albedo[l];
+            optics[l].g = (Real)m->g[l];
+            optics[l].L0 = (Real)((dust ? dust->L[l] : s->source->L[l]) / (double)n_per_lambda);
+            optics[l].lamf = (Real)s->lamf[l];
+        }
+        HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_fill_zero(r->d_counter, sizeof(unsigned long long), st));
     }
-    HIP_TRY(hipMemcpyAsync(s->d_optics, optics.data(), optics.size() * sizeof(Optics<Real>), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_fill_zero(r->d_counter, sizeof(unsigned long long), st));
 
     TransportArgs<Real, ImgT, G> a{};
     View<Real, ImgT, G> &v = a.view;
@@ -726,7 +760,8 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         v.hist_total = (Real *)hist->d_total;
         v.hist_events = hist->events;
     }
-    a.optics = (const Optics<Real> *)s->d_optics;
+    a.optics = scratch ? (const Optics<Real> *)((const unsigned char *)scratch + kNoAllocHeader)
+                       : (const Optics<Real> *)s->d_optics;
     a.ins = (const InsDesc<Real> *)s->d_ins;
     a.count = count;
     a.first_id = first_id;
@@ -739,7 +774,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     auto_chunk = auto_chunk < 32 ? 32 : (auto_chunk > 256 ? 256 : auto_chunk);
     a.chunk = (uint32_t)(s->opt.chunk > 0 ? (uint64_t)s->opt.chunk : auto_chunk);
     a.threshold = s->opt.threshold > 0 ? s->opt.threshold : 16;
-    a.counter = r->d_counter;
+    a.counter = scratch ? (unsigned long long *)scratch : r->d_counter;
     a.energy = r->d_energy;
     a.stats = r->d_stats;
     uint64_t chunks = (a.total + a.chunk - 1) / a.chunk;
@@ -747,21 +782,29 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     int grid = (int)((waves + (kBlock / 64) - 1) / (kBlock / 64));
     if (grid < 1) grid = 1;
 
-    EventPair ev;
-    HIP_TRY(hipEventCreate(&ev.e0));
-    HIP_TRY(hipEventCreate(&ev.e1));
-    HIP_TRY(hipEventRecord(ev.e0, st));
-    hipError_t le;
-    if constexpr (sizeof(Real) == 4 && G == kCartesian) le = launch_transport_f32c(a, grid, st);
-    else if constexpr (sizeof(Real) == 4) le = launch_transport_f32o(a, grid, st);
-    else if constexpr (G == kCartesian) le = launch_transport_f64c(a, grid, st);
-    else le = launch_transport_f64o(a, grid, st);
-    HIP_TRY(le);
-    HIP_TRY(hipEventRecord(ev.e1, st));
-    HIP_TRY(hipEventSynchronize(ev.e1));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
-    r->kernel_ms = ms;
+    auto launch = [&]() -> hipError_t {
+        if constexpr (sizeof(Real) == 4 && G == kCartesian) return launch_transport_f32c(a, grid, st);
+        else if constexpr (sizeof(Real) == 4) return launch_transport_f32o(a, grid, st);
+        else if constexpr (G == kCartesian) return launch_transport_f64c(a, grid, st);
+        else return launch_transport_f64o(a, grid, st);
+    };
+    if (scratch) {
+        // no events (creating them allocates): the launch is not timed
+        HIP_TRY(launch());
+        HIP_TRY(hipStreamSynchronize(st));
+        r->kernel_ms = 0.0;
+    } else {
+        EventPair ev;
+        HIP_TRY(hipEventCreate(&ev.e0));
+        HIP_TRY(hipEventCreate(&ev.e1));
+        HIP_TRY(hipEventRecord(ev.e0, st));
+        HIP_TRY(launch());
+        HIP_TRY(hipEventRecord(ev.e1, st));
+        HIP_TRY(hipEventSynchronize(ev.e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        r->kernel_ms = ms;
+    }
     unsigned long long stats[kNumStats];
     HIP_TRY(hipMemcpy(stats, r->d_stats, sizeof(stats), hipMemcpyDeviceToHost));
     return launch_outcome(r, stats);
@@ -803,6 +846,36 @@ int mcrt_run_into(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint6
     }
     if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res);
     return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res);
+}
+
+int mcrt_run_into_noalloc(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed,
+                          mcrt_result *res)
+{
+    if (!sim || !res) return fail(MCRT_EINVAL, "run_into_noalloc: NULL sim or result");
+    if (res->sim != sim) return fail(MCRT_EINVAL, "run_into_noalloc: result belongs to another sim");
+    if (n_per_lambda == 0 || n_per_lambda > (uint64_t(1) << 32))
+        return fail(MCRT_EINVAL, "run_into_noalloc: n_per_lambda must be in 1 .. 2^32");
+    if (first_id > n_per_lambda || count > n_per_lambda - first_id)
+        return fail(MCRT_EINVAL, "run_into_noalloc: id range exceeds n_per_lambda");
+    if (sim->medium->n_lambda > kNoAllocMaxLambda)
+        return fail(MCRT_EINVAL, "run_into_noalloc: at most 4096 wavelengths (the scratch array's size)");
+    BusyGuard guard(sim->busy);
+    if (!guard.owned) return fail(MCRT_EBUSY, "run_into_noalloc: the simulation is already running");
+    if (count == 0) return MCRT_OK;
+    HIP_TRY(hipSetDevice(sim->ctx->device));
+    void *scratch = noalloc_scratch(sim->ctx->device);
+    if (!scratch) return fail(MCRT_EDEVICE, "run_into_noalloc: no scratch address for this device");
+    const bool oct = sim->medium->grid->type == kOctree;
+    if (sim->opt.precision == MCRT_FP32) {
+        if (oct) return run_impl<float, float, kOctree>(sim, n_per_lambda, first_id, count, seed, res, nullptr,
+                                                         nullptr, scratch);
+        return run_impl<float, float, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, nullptr,
+                                                  scratch);
+    }
+    if (oct) return run_impl<double, double, kOctree>(sim, n_per_lambda, first_id, count, seed, res, nullptr,
+                                                       nullptr, scratch);
+    return run_impl<double, double, kCartesian>(sim, n_per_lambda, first_id, count, seed, res, nullptr, nullptr,
+                                                scratch);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,7 +28,8 @@ EXPORTS = [
     "mcrt_medium_create", "mcrt_medium_destroy", "mcrt_source_create_point",
     "mcrt_source_create_expdisk", "mcrt_source_destroy", "mcrt_instrument_create",
     "mcrt_instrument_destroy", "mcrt_sim_create", "mcrt_sim_destroy", "mcrt_result_create",
-    "mcrt_result_zero", "mcrt_run_into", "mcrt_run", "mcrt_run_range", "mcrt_result_absorption",
+    "mcrt_result_zero", "mcrt_run_into", "mcrt_run_into_noalloc", "mcrt_run", "mcrt_run_range",
+    "mcrt_result_absorption",
     "mcrt_result_image", "mcrt_result_energy", "mcrt_result_stats", "mcrt_result_destroy",
     "mcrt_sim_info", "mcrt_last_error", "mcrt_microbench", "mcrt_microbench_error",
     "mcrt_batch_run_into", "mcrt_sim_set_tuning", "mcrt_autotune",
@@ -131,6 +132,8 @@ def lib():
         "mcrt_result_create": (ctypes.c_int, [P, PP]),
         "mcrt_result_zero": (ctypes.c_int, [P]),
         "mcrt_run_into": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, P]),
+        "mcrt_run_into_noalloc": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_uint64, P]),
         "mcrt_run": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, PP]),
         "mcrt_run_range": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
@@ -481,6 +484,15 @@ class Sim:
             count = n_per_lambda - first_id
         return _check(lib().mcrt_run_into(self.h, int(n_per_lambda), int(first_id), int(count),
                                           int(seed), result.h), allow=(ELIMIT, ENONFINITE))
+
+    def run_into_noalloc(self, result: Result, n_per_lambda: int, seed: int = 0, first_id: int = 0,
+                         count: Optional[int] = None) -> int:
+        """run_into through the allocation-free entry point (the library's
+        per-GPU scratch array; no allocation, no host copy, not timed)."""
+        if count is None:
+            count = n_per_lambda - first_id
+        return _check(lib().mcrt_run_into_noalloc(self.h, int(n_per_lambda), int(first_id), int(count),
+                                                  int(seed), result.h), allow=(ELIMIT, ENONFINITE))
 
     def run(self, n_per_lambda: int, seed: int = 0, first_id: int = 0,
             count: Optional[int] = None) -> Result:

@@ -11,7 +11,9 @@ already resident in HBM.
 Prints ONE JSON line with packets/s, the roofline of the transport kernel
 (algorithmic bytes from the kernel's own cell/pixel counters over its HIP-event
 duration, against 8 TB/s HBM) and the FP64 CPU oracle timed on the host cores
-on a bounded sample.
+on a bounded sample; then the metric's second half, the image RMS error x
+time of the learned direction proposal against the plain sampler on the
+clumpy torus (learned_vs_plain; --no-learned skips it).
 """
 from __future__ import annotations
 
@@ -80,6 +82,9 @@ def bench_batch(args):
     import torch
     from paper_1705_04702_amd import mcrt, scenes
     models = scenes.batch(256, seed=4)
+    if args.tau_peel_max is not None:
+        for m in models:
+            m.scene.tau_peel_max = args.tau_peel_max
     ctx = mcrt.Context(0)
     order = {"cost": mcrt.QUEUE_COST, "caller": mcrt.QUEUE_CALLER, "paired": mcrt.QUEUE_PAIRED}[args.queue_order]
     sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32, chunk=args.chunk or None, waves_per_cu=args.waves_per_cu or None,
@@ -133,6 +138,8 @@ def bench_dust(args):
     import torch
     from paper_1705_04702_amd import mcrt, scenes
     scene = scenes.disk()
+    if args.tau_peel_max is not None:
+        scene.tau_peel_max = args.tau_peel_max
     N = WORKLOADS["disk"][0]
     B = min(args.step_packets, N)
     nl = scene.n_lambda
@@ -199,7 +206,7 @@ def _image_cube(res, n_ins):
     return np.concatenate([res.image(j).ravel() for j in range(n_ins)])
 
 
-def bench_learned(args):
+def learned_vs_plain(args):
     """Learned direction proposal on the clumpy-torus workload: collect plain
     histories (1e7 packets, seed 1), train the network (Adam, lr 1e-3), then
     compare the image error of a learned run (1e8 packets, seed 2) with a
@@ -208,11 +215,14 @@ def bench_learned(args):
     sqrt(sum I_ref^2) over all pixels and wavelengths, with the reference's
     own noise (from its two halves) subtracted; figure of merit 1 / (RMS^2 t)
     with t the transport time.  Collection and training are reported
-    separately."""
+    separately.  Returns (learned packets/s, learned seconds, the comparison,
+    the configuration)."""
     import numpy as np
     import torch
     from paper_1705_04702_amd import mcrt, scenes
     sc = scenes.torus()
+    if args.tau_peel_max is not None:
+        sc.tau_peel_max = args.tau_peel_max
     nl = sc.n_lambda
     n_hist = args.hist_packets // nl
     n_learn = args.learned_packets // nl
@@ -287,26 +297,36 @@ def bench_learned(args):
     tot_l, tot_p, tot_r = float(learned.sum()), float(plain.sum()), float(ref.sum())
     log(f"rms learned {rms_l:.4e} ({t_learned:.2f} s), plain {rms_p:.4e} ({t_plain:.2f} s), "
         f"gain {fom_l / fom_p:.3f}")
-    out = {"metric": METRIC, "value": n_learn * nl / t_learned, "unit": "packets/s", "n_gpus": 1,
-           "steps": 1, "warmup": 0, "ms_per_step": t_learned * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
-           "config": {"workload": "clumpy AGN torus (octree ~2.2e6 leaves, 32 wavelengths, 1024^2 edge-on "
-                                  "instrument) with the learned vMF-mixture direction proposal",
-                      "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
-                      "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
-                      "alpha": 0.2, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
-                      "max_events": args.max_events},
-           "learned_vs_plain": {"rms_learned": rms_l, "rms_plain": rms_p, "t_learned_s": t_learned,
-                                "t_plain_s": t_plain, "rms2_t_learned": rms_l ** 2 * t_learned,
-                                "rms2_t_plain": rms_p ** 2 * t_plain, "fom_gain": fom_l / fom_p,
-                                "flux_learned_over_ref": tot_l / tot_r, "flux_plain_over_ref": tot_p / tot_r,
-                                "reference_noise_fraction": noise / ref2,
-                                "collect_s": t_collect, "train_s": t_train, "loss_before": loss0,
-                                "loss_after": loss1, "counters_per_packet": counters,
-                                "energy_balance_learned":
-                                    abs(e_learned[0] - e_learned[1] - e_learned[2] - e_learned[3]) / e_learned[0]}}
+    config = {"workload": "clumpy AGN torus (octree ~2.2e6 leaves, 32 wavelengths, 1024^2 edge-on "
+                          "instrument) with the learned vMF-mixture direction proposal",
+              "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
+              "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
+              "alpha": 0.2, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+              "max_events": args.max_events, "tau_peel_max": sc.tau_peel_max}
+    cmp = {"rms_learned": rms_l, "rms_plain": rms_p, "t_learned_s": t_learned,
+           "t_plain_s": t_plain, "rms2_t_learned": rms_l ** 2 * t_learned,
+           "rms2_t_plain": rms_p ** 2 * t_plain, "fom_gain": fom_l / fom_p,
+           "fom_gain_with_training": (rms_p ** 2 * t_plain) / (rms_l ** 2 * (t_learned + t_collect + t_train)),
+           "flux_learned_over_ref": tot_l / tot_r, "flux_plain_over_ref": tot_p / tot_r,
+           "reference_noise_fraction": noise / ref2,
+           "collect_s": t_collect, "train_s": t_train, "loss_before": loss0,
+           "loss_after": loss1, "counters_per_packet": counters,
+           "energy_balance_learned":
+               abs(e_learned[0] - e_learned[1] - e_learned[2] - e_learned[3]) / e_learned[0],
+           "workload": config["workload"], "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
+           "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl}
     prop.close()
     sim.close()
+    return n_learn * nl / t_learned, t_learned, cmp, config
+
+
+def bench_learned(args):
+    """The learned-proposal workload on its own: value = learned packets/s."""
+    rate, t_learned, cmp, config = learned_vs_plain(args)
+    out = {"metric": METRIC, "value": rate, "unit": "packets/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": t_learned * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "config": config, "learned_vs_plain": cmp}
     print(json.dumps(out), flush=True)
 
 
@@ -385,7 +405,10 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
     import oracle
     oracle.lib()
     _SC = scene
-    cores = min(16, os.cpu_count() or 1)
+    # P = nproc (the CPUs this process may run on), within the host's share of
+    # 16 CPUs per GPU
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, nproc))
     # calibrate on one task
     t0 = time.perf_counter()
     _oracle_task((scene.n_lambda // 2, n_per_lambda, 50, 0))
@@ -410,7 +433,7 @@ def cpu_baseline(scene, n_per_lambda, seconds_target=15.0):
                       f"{cores} processes",
             "single_core": {"value": single, "unit": "packets/s",
                             "sample": f"packet ids [0, {c1}) of wavelengths {lams}, one process"},
-            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()}}
+            "host": {"nproc": nproc, "cpu_count": os.cpu_count(), "cpu_model": _cpu_model()}}
 
 
 def microbenchmarks():
@@ -457,6 +480,10 @@ def main():
     ap.add_argument("--batch", type=int, default=16384, help="torus-learned: samples per Adam step")
     ap.add_argument("--lr", type=float, default=1e-3, help="torus-learned: Adam learning rate")
     ap.add_argument("--max-events", type=int, default=16, help="torus-learned: recorded events per packet")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="default line: skip the learned-vs-plain comparison on the torus")
+    ap.add_argument("--tau-peel-max", type=float, default=None,
+                    help="peel-off optical-depth cut (default: none, every peel-off counts)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -492,6 +519,8 @@ def main():
         bench_dust(args)
         return
     scene, workload = make_scene(args.workload)
+    if args.tau_peel_max is not None:
+        scene.tau_peel_max = args.tau_peel_max
     N = args.n_per_lambda or WORKLOADS[args.workload][0]
     if args.curve:
         bench_curve(args, scene, workload, N)
@@ -574,7 +603,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n_per_lambda": N, "packets_per_step": B * nl,
                    "grid": list(scene.n), "n_lambda": nl,
-                   "instruments": [list(i.npix) for i in scene.instruments]},
+                   "instruments": [list(i.npix) for i in scene.instruments],
+                   "tau_peel_max": scene.tau_peel_max},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "atomic_roofline": {"achieved": req_per_s, "peak": atomic_ceiling, "unit": "atomic requests/s",
@@ -588,6 +618,26 @@ def main():
     }
     res.close()
     sim.close()
+    # The same kernel against what this device measurably sustains, in this
+    # run: a streaming copy, and random 4-byte gathers over a working set the
+    # size of the density array (useful bytes only); 8 TB/s is context.
+    copy_Bps = mcrt.microbench("copy", 1 << 30)
+    gathers = mcrt.microbench("gather4", max(4 * scene.n_cells, 1 << 21), 1 << 28)
+    traffic_GBps = traffic / avg_kernel_s / 1e9 if traffic else None
+    out["bandwidth_context"] = {
+        "copy_GBps": copy_Bps / 1e9, "random_gather_useful_GBps": 4 * gathers / 1e9,
+        "random_gathers_per_s": gathers, "gather_working_set_bytes": max(4 * scene.n_cells, 1 << 21),
+        "algorithmic_GBps": achieved, "algorithmic_over_copy": achieved / (copy_Bps / 1e9),
+        "algorithmic_over_random_gather": achieved / (4 * gathers / 1e9),
+        "measured_traffic_GBps": traffic_GBps,
+        "measured_traffic_over_copy": traffic_GBps / (copy_Bps / 1e9) if traffic_GBps else None,
+        "note": "algorithmic = the roofline's bytes; measured traffic = FETCH_SIZE + WRITE_SIZE of the "
+                "committed profile (null when the kernel changed since); the deposits' bound is the "
+                "atomic_roofline"}
+    if args.workload == "disk" and not args.no_learned:
+        print("[bench] learned vs plain on the torus (the metric's second half)", file=sys.stderr, flush=True)
+        _, _, cmp, _ = learned_vs_plain(args)
+        out["learned_vs_plain"] = cmp
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, N)

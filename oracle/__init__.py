@@ -99,9 +99,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+        # MCRT_ORACLE_LIB: another build of the same source (the sanitizer
+        # build of the CPU tests)
+        path = os.environ.get("MCRT_ORACLE_LIB")
+        if not path:
+            if not os.path.exists(_LIB_PATH):
+                build()
+            path = _LIB_PATH
+        L = ctypes.CDLL(path)
         L.or_run.argtypes = [ctypes.POINTER(_Scene), ctypes.c_uint64, ctypes.c_uint64,
                              ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_Out)]
         L.or_run.restype = ctypes.c_int

@@ -45,10 +45,13 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(PATH):
-            from paper_1705_04702_amd import build
-            build.build_lanesim()
-        _lib = ctypes.CDLL(PATH)
+        path = os.environ.get("MCRT_LANESIM_LIB")  # the sanitizer build of the CPU tests
+        if not path:
+            if not os.path.exists(PATH):
+                from paper_1705_04702_amd import build
+                build.build_lanesim()
+            path = PATH
+        _lib = ctypes.CDLL(path)
         _lib.ls_run.argtypes = [ctypes.POINTER(_Scene), ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(_Out)]
         _lib.ls_run.restype = ctypes.c_int

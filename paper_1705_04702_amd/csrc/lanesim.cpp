@@ -152,12 +152,19 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
         HostInstrument h{gm[0], gm[1], gm[2], {gm[3], gm[4]}, {s->ins_npix[2 * j], s->ins_npix[2 * j + 1]}};
         make_ins_desc<Real>(h, off, ins[j], inv4pid2[j]);
         off += (long long)s->n_lambda * h.npix[0] * h.npix[1];
-        const int code = G == kCartesian ? axis_code(h) : -1;
+        const int code = (G == kCartesian || depth <= kMaxColumnDepth) ? axis_code(h) : -1;
         if (code >= 0) {
-            std::vector<double> S;
-            int n3[3] = {s->n[0], s->n[1], s->n[2]};
-            column_map(s->density, n3, s->box, code, v.bs, v.sh, v.nb, v.n_store, S);
-            cols[j].assign(S.begin(), S.end());
+            if (G == kCartesian) {
+                std::vector<double> S;
+                int n3[3] = {s->n[0], s->n[1], s->n[2]};
+                column_map(s->density, n3, s->box, code, v.bs, v.sh, v.nb, v.n_store, S);
+                cols[j].assign(S.begin(), S.end());
+            } else {
+                std::vector<int32_t> onode;
+                std::string err;
+                if (encode_octree(s->n_nodes, s->first_child, s->n_cells, onode, err) < 0) return -2;
+                octree_column_map<Real>(onode, depth, s->n_cells, s->density, s->box, code, cols[j]);
+            }
             ins[j].col = cols[j].data();
             ins[j].col_axis = code;
         }

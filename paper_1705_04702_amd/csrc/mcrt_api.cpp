@@ -466,13 +466,26 @@ template <typename Real> static int upload_instruments(mcrt_sim *s)
 {
     std::vector<InsDesc<Real>> d((size_t)std::max(s->n_ins, 1));
     const mcrt_grid *g = s->medium->grid;
+    // octree lattice column maps need the encoded tree (depth <= 10: at most
+    // 2^30 lattice cells per map)
+    std::vector<int32_t> onode;
+    if (g->type == kOctree && s->depth <= kMaxColumnDepth) {
+        std::string err;
+        if (encode_octree((int64_t)g->first_child.size(), g->first_child.data(), g->n_cells, onode, err) < 0)
+            return fail(MCRT_EINVAL, "sim_create: " + err);
+    }
     for (int j = 0; j < s->n_ins; ++j) {
         make_ins_desc<Real>(s->ins[j], s->ins_offset[j], d[j], s->inv4pid2[j]);
-        const int code = g->type == kCartesian ? axis_code(s->ins[j]) : -1;
+        const int code = (g->type == kCartesian || !onode.empty()) ? axis_code(s->ins[j]) : -1;
         if (code < 0) continue;
-        std::vector<double> S;
-        column_map(s->medium->density.data(), g->n, g->box, code, s->bs, s->sh, s->nb, s->n_store, S);
-        std::vector<Real> Sr(S.begin(), S.end());
+        std::vector<Real> Sr;
+        if (g->type == kCartesian) {
+            std::vector<double> S;
+            column_map(s->medium->density.data(), g->n, g->box, code, s->bs, s->sh, s->nb, s->n_store, S);
+            Sr.assign(S.begin(), S.end());
+        } else {
+            octree_column_map<Real>(onode, s->depth, g->n_cells, s->medium->density.data(), g->box, code, Sr);
+        }
         int rc = dev_alloc(&s->d_col[j], Sr.size() * sizeof(Real));
         if (rc) return rc;
         HIP_TRY(hipMemcpy(s->d_col[j], Sr.data(), Sr.size() * sizeof(Real), hipMemcpyHostToDevice));

@@ -376,4 +376,50 @@ inline void column_map(const float *density, const int n[3], const double box[6]
         }
 }
 
+// Octree grids, line of sight along a lattice axis (code = 2 axis + (k < 0),
+// as axis_code): S[x + N (y + N z)] (N = 2^depth lattice cells per axis) =
+// sum of density x width over the lattice cells from (x, y, z) itself up to
+// the boundary on the observer's side (every lattice cell of a leaf has the
+// leaf's density).  A peel-off from a point of lattice cell c then has the
+// optical depth kappa (S[c'] + (S[c] - S[c']) f), c' the next lattice cell
+// towards the observer (S = 0 past the boundary) and f the fraction of c's
+// width still to cross: two reads instead of a march through the leaves.
+template <typename Real>
+inline void octree_column_map(const std::vector<int32_t> &node, int depth, int64_t n_leaves, const float *density,
+                              const double box[6], int code, std::vector<Real> &S)
+{
+    const int a = code >> 1;
+    const bool neg = (code & 1) != 0;
+    const int64_t N = int64_t(1) << depth;
+    std::vector<int32_t> geo;
+    leaf_geometry(node, depth, n_leaves, geo);
+    std::vector<float> lat((size_t)(N * N * N), 0.0f);
+    for (int64_t l = 0; l < n_leaves; ++l) {
+        const int64_t x0 = geo[(size_t)l * 4], y0 = geo[(size_t)l * 4 + 1], z0 = geo[(size_t)l * 4 + 2];
+        const int64_t size = int64_t(1) << (depth - geo[(size_t)l * 4 + 3]);
+        const float rho = density[l];
+        for (int64_t z = z0; z < z0 + size; ++z)
+            for (int64_t y = y0; y < y0 + size; ++y)
+                for (int64_t x = x0; x < x0 + size; ++x) lat[(size_t)(x + N * (y + N * z))] = rho;
+    }
+    const int u = (a + 1) % 3, w = (a + 2) % 3;
+    int64_t st[3] = {1, N, N * N};
+    const double cs = (box[3 + a] - box[a]) / (double)N;
+    S.assign((size_t)(N * N * N), Real(0));
+    for (int64_t iw = 0; iw < N; ++iw)
+        for (int64_t iu = 0; iu < N; ++iu) {
+            double acc = 0.0;
+            for (int64_t s = 0; s < N; ++s) {
+                const int64_t ia = neg ? s : N - 1 - s; // from the observer's side of the grid inwards
+                const int64_t idx = ia * st[a] + iu * st[u] + iw * st[w];
+                const double lo = box[a] + (double)ia * cs, hi = box[a] + (double)(ia + 1) * cs;
+                acc = acc + (double)lat[(size_t)idx] * (hi - lo);
+                S[(size_t)idx] = (Real)acc;
+            }
+        }
+}
+
+// Largest octree depth whose lattice column maps are built (8^10 cells).
+constexpr int kMaxColumnDepth = 10;
+
 } // namespace mcrt

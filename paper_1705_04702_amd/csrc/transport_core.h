@@ -113,10 +113,11 @@ template <typename Real> struct InsDesc {
     int nx, ny;
     long long offset; // first image element of this instrument
     Real inv4pid2;    // flux per unit of image accumulation
-    // Cartesian grids, line of sight along a grid axis: col[store(c)] = sum of
-    // density x path length over the cells beyond c up to the boundary, so a
-    // peel-off's optical depth needs no march; col_axis = 2 axis + (k < 0),
-    // -1 (col == nullptr) otherwise
+    // Line of sight along a grid axis, so a peel-off's optical depth needs no
+    // march.  Cartesian grids: col[store(c)] = sum of density x path length
+    // over the cells beyond c up to the boundary; octree grids (depth <= 10):
+    // col[x + N (y + N z)] = the same sum over lattice cells from (x, y, z)
+    // itself.  col_axis = 2 axis + (k < 0), -1 (col == nullptr) otherwise
     const Real *col;
     int col_axis;
 };
@@ -675,6 +676,28 @@ MCRT_HD Real column_tau(const View<Real, ImgT, G> &v, const Lane<Real> &ln, cons
     return ln.opt.kappa * ((Real)gload(v.density, cell) * (tn - ln.t) + gload(col, cell));
 }
 
+// Octree grids: optical depth to the boundary along lattice axis A from the
+// march start, from the cumulative column at lattice resolution (col[c] =
+// density x width summed from lattice cell c itself to the boundary on the
+// observer's side): the next cell's column plus the part of this cell's
+// (their difference) still to cross.
+template <int A, typename Real, typename ImgT, int G>
+MCRT_HD Real octree_column_tau(const View<Real, ImgT, G> &v, const Lane<Real> &ln, const Real *col)
+{
+    const long long N = v.n[0];
+    const long long idx = (long long)ln.c0 + N * ((long long)ln.c1 + N * (long long)ln.c2);
+    const int c = A == 0 ? ln.c0 : (A == 1 ? ln.c1 : ln.c2);
+    const bool neg = ln.d[A] < Real(0);
+    const long long stride = A == 0 ? 1 : (A == 1 ? N : N * N);
+    const bool has_next = (unsigned)(neg ? c - 1 : c + 1) < (unsigned)N;
+    const Real Sc = gload(col, idx);
+    const Real Sn = gload(col, has_next ? (neg ? idx - stride : idx + stride) : idx);
+    const Real Snext = has_next ? Sn : Real(0);
+    Real f = Prec<Real>::over_k(plane_t(v, ln, A, neg ? c : c + 1) - ln.t, v.cs[A], v.ics[A]);
+    f = f < Real(0) ? Real(0) : (f > Real(1) ? Real(1) : f);
+    return ln.opt.kappa * (Snext + (Sc - Snext) * f);
+}
+
 template <typename Real, typename ImgT, int G>
 MCRT_HD void begin_peel(const View<Real, ImgT, G> &v, Lane<Real> &ln, int j, bool emission)
 {
@@ -703,6 +726,18 @@ MCRT_HD void begin_peel(const View<Real, ImgT, G> &v, Lane<Real> &ln, int j, boo
             if (a == 0) tau = column_tau<0>(v, ln, in.col);
             else if (a == 1) tau = column_tau<1>(v, ln, in.col);
             else tau = column_tau<2>(v, ln, in.col);
+            ln.tau = tau;
+            ln.dropped = tau >= v.tau_peel_max;
+            ln.nseg = 1;
+            ln.marching = false;
+        }
+    } else {
+        if (in.col != nullptr && ln.marching) {
+            const int a = in.col_axis >> 1;
+            Real tau;
+            if (a == 0) tau = octree_column_tau<0>(v, ln, in.col);
+            else if (a == 1) tau = octree_column_tau<1>(v, ln, in.col);
+            else tau = octree_column_tau<2>(v, ln, in.col);
             ln.tau = tau;
             ln.dropped = tau >= v.tau_peel_max;
             ln.nseg = 1;

@@ -147,12 +147,39 @@ template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
     }
 };
 
+// Second level of the pixel accumulation: one pixel per wave whose combined
+// adds are summed in FP64 across flushes and added to the image once that
+// pixel stops being the wave's combined pixel, and when the wave ends (or
+// leaves the model's images).  The carry lives in a per-wave LDS slot (no
+// registers held across the event loop): every lane reads it, lane 0 writes
+// it; one wave's LDS operations complete in order.
+struct PixelCarry {
+    long long key; // image element, -1 when empty
+    double val;
+};
+
+__device__ __forceinline__ void carry_init(PixelCarry *c, int lane)
+{
+    if (lane == 0) {
+        c->key = -1;
+        c->val = 0.0;
+    }
+}
+
+template <typename ImgT> __device__ __forceinline__ void flush_carry(PixelCarry *c, ImgT *images, int lane)
+{
+    const long long key = c->key;
+    const double val = c->val;
+    if (key >= 0 && lane == 0) unsafeAtomicAdd(images + key, (ImgT)val);
+    carry_init(c, lane);
+}
+
 // Wave-level combine of the pending pixel adds: the lanes whose pixel equals
-// the first pending lane's pixel are summed across the wave and added once
-// (a point source's emission peel-offs all land in one pixel per
-// wavelength); the other lanes add their own.  Whole wave active.
+// the first pending lane's pixel are summed across the wave (a point
+// source's emission peel-offs all land in one pixel per wavelength) and
+// join the wave's carry; the other lanes add their own.  Whole wave active.
 template <typename Real, typename ImgT>
-__device__ __forceinline__ void flush_pixels(Lane<Real> &ln, ImgT *images, int lane)
+__device__ __forceinline__ void flush_pixels(Lane<Real> &ln, ImgT *images, int lane, PixelCarry *c)
 {
     const unsigned long long m = __ballot(ln.pix >= 0);
     if (m == 0) return;
@@ -161,8 +188,14 @@ __device__ __forceinline__ void flush_pixels(Lane<Real> &ln, ImgT *images, int l
     const bool same = ln.pix == key;
     ImgT s = same ? (ImgT)ln.pval : (ImgT)0;
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == leader) unsafeAtomicAdd(images + key, s);
-    else if (ln.pix >= 0 && !same) unsafeAtomicAdd(images + ln.pix, (ImgT)ln.pval);
+    const long long ckey = c->key;
+    const double cval = c->val;
+    if (ckey >= 0 && ckey != key && lane == leader) unsafeAtomicAdd(images + ckey, (ImgT)cval);
+    if (lane == leader) {
+        c->key = key;
+        c->val = (ckey == key ? cval : 0.0) + (double)s;
+    }
+    if (ln.pix >= 0 && !same) unsafeAtomicAdd(images + ln.pix, (ImgT)ln.pval);
     ln.pix = -1;
 }
 
@@ -280,6 +313,9 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     ln.parked = false;
     ln.pix = -1;
     Tally ty = {};
+    __shared__ PixelCarry s_carry[kBlock / 64];
+    PixelCarry *carry = s_carry + wave;
+    carry_init(carry, lane);
     uint64_t cur = 0, end = 0;
     bool exhausted = false;
 
@@ -330,7 +366,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
                 }
             }
         }
-        flush_pixels(ln, v.images, lane);
+        flush_pixels(ln, v.images, lane, carry);
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;
@@ -348,6 +384,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
         }
     }
 
+    flush_carry(carry, v.images, lane);
     double e0 = wave_sum(ty.emitted), e1 = wave_sum(ty.absorbed);
     double e2 = wave_sum(ty.escaped), e3 = wave_sum(ty.truncated);
     unsigned long long s[kNumStats] = {ty.packets, ty.events, ty.prop_cells, ty.locate_cells,
@@ -437,6 +474,9 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
     ln.marching = false;
     ln.pix = -1;
     Tally ty = {};
+    __shared__ PixelCarry s_carry[kBlock / 64];
+    PixelCarry *carry = s_carry + wave;
+    carry_init(carry, lane);
     int cur_model = -1, pend_model = -1;
     // The current model's view is read through a constant-address-space
     // pointer formed from a wave-uniform model index at every use: its fields
@@ -480,8 +520,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
                 }
                 if (pend_model != cur_model) {
                     if (__ballot(ln.mode != kDead) != 0) break; // drain before switching
-                    if (cur_model >= 0)
+                    if (cur_model >= 0) {
+                        flush_carry(carry, V().images, lane);
                         flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
+                    }
                     cur_model = pend_model;
                     const ModelDesc<Real, ImgT> &m = a.models[cur_model];
                     count = m.count;
@@ -503,7 +545,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
             cur += ndead < avail ? ndead : avail;
         }
         if (!ln.marching && ln.mode != kDead) settle(V(), ln, ty, sink);
-        flush_pixels(ln, V().images, lane);
+        flush_pixels(ln, V().images, lane, carry);
         if (__ballot(ln.mode != kDead) == 0) {
             if (exhausted) break;
             continue;
@@ -517,7 +559,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
             if (active == 0 || __popcll(waiting) >= a.threshold) break;
         }
     }
-    if (cur_model >= 0) flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
+    if (cur_model >= 0) {
+        flush_carry(carry, V().images, lane);
+        flush_tally<Real, ImgT, 0>(ty, a.models[cur_model].energy, a.models[cur_model].stats, lane);
+    }
 }
 
 // FP32: four waves per SIMD (128 VGPRs, a few registers spilled): the

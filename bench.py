@@ -78,7 +78,9 @@ def make_scene(name: str):
 
 def bench_batch(args):
     """256 uneven uniform-sphere / exponential-slab models (16^3 .. 128^3,
-    1e5 .. 1e7 packets each, 128^2 images) in one persistent launch per step."""
+    1e5 .. 1e7 packets each, 128^2 images) in one persistent launch per step,
+    with the queue tuned by the library's autotuner first (cached by problem
+    class; --no-autotune keeps the defaults)."""
     import torch
     from paper_1705_04702_amd import mcrt, scenes
     models = scenes.batch(256, seed=4)
@@ -91,8 +93,10 @@ def bench_batch(args):
                      threshold=args.threshold or None, queue_order=order) for m in models]
     npl = [m.n_packets for m in models]
     tuning = None
-    if args.autotune:
-        tuning = mcrt.autotune(sims, [max(1, n // 100) for n in npl], seed=0,
+    if not args.no_autotune:
+        # trials of an eighth of every model's packets: the shape of the full
+        # launch (its tail weighs more in a short trial)
+        tuning = mcrt.autotune(sims, [max(1, n // 8) for n in npl], seed=0,
                                cache_path=os.path.join(ROOT, "_build", "tune_cache.txt"))
         print(f"[bench] autotune {tuning}", file=sys.stderr, flush=True)
     res = [s.new_result() for s in sims]
@@ -458,7 +462,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="disk")
     ap.add_argument("--n-per-lambda", type=int, default=0, help="0 = the workload's own")
-    ap.add_argument("--autotune", action="store_true", help="tune the queue before timing")
+    ap.add_argument("--autotune", action="store_true", help="tune the queue before timing (batch: always)")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: time the library's default queue")
     ap.add_argument("--step-packets", type=int, default=1_000_000,
                     help="packet ids per wavelength in one step")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -246,22 +246,29 @@ int mcrt_run_range(mcrt_sim *sim, uint64_t n_per_lambda, uint64_t first_id, uint
 int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_lambda, uint64_t seed,
                         mcrt_result *const *results);
 
-/* Launch tuning of a sim (overrides its options' queue parameters). */
+/* Launch tuning of a sim (overrides its options' queue parameters; the work
+ * distribution of Section 5.2.4: how many packets a thread takes per grab). */
 typedef struct {
-    int32_t chunk;        /* packets per work-queue grab */
+    int32_t chunk;        /* packets per work-queue grab; 0 = the automatic chunk */
     int32_t waves_per_cu; /* persistent waves per compute unit */
     int32_t threshold;    /* lanes that must finish a march before events run */
     double kernel_ms;     /* trial time of this setting (output of the tuner) */
     int32_t from_cache;   /* 1 if the tuner found the setting in its cache */
+    double default_ms;    /* trial time of the library's defaults (output of the tuner) */
 } mcrt_tuning;
 
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
 
-/* Autotuner: coordinate search over chunk ({32..2048} for one sim,
- * {256..16384} for a batch), threshold {8..48} and
- * waves per CU {8, 12, 16} with short trial runs of trial_packets[i] packets
- * per wavelength of each sim (one sim: the single-model kernel; several: the
- * batched kernel), keeping the fastest.  With cache_path (may be NULL) the
+/* Autotuner: coordinate search, starting from sims[0]'s options (the
+ * library's defaults unless set), over chunk ({auto, 32..2048} for one sim,
+ * {auto, 256..16384} for a batch), threshold {8..48} and waves per CU
+ * {8, 12, 16} with trial runs of trial_packets[i] packets per wavelength of
+ * each sim (one sim: the single-model kernel; several: the batched kernel),
+ * keeping the fastest; the pick and the defaults are then timed twice more
+ * each and the pick is kept only if its best time beats the defaults' (both
+ * times are returned).  Trials should be long enough to have the full
+ * launch's shape (a launch's tail weighs more in a short trial).  With
+ * cache_path (may be NULL) the
  * result is stored under a key describing the problem class (grid type,
  * precision, model count, cells, wavelengths, instruments) and reused on the
  * next call without trials.  The tuning is applied to every sim and returned

@@ -1284,7 +1284,7 @@ int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t)
 {
     if (!sim || !t) return fail(MCRT_EINVAL, "sim_set_tuning: NULL argument");
-    if (t->chunk <= 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64)
+    if (t->chunk < 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64)
         return fail(MCRT_EINVAL, "sim_set_tuning: values out of range");
     sim->opt.chunk = t->chunk;
     sim->opt.waves_per_cu = t->waves_per_cu;
@@ -1324,8 +1324,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
                 if (!bar) continue;
                 *bar = 0;
                 mcrt_tuning t{};
-                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf", &t.chunk, &t.waves_per_cu, &t.threshold,
-                                               &t.kernel_ms) == 4) {
+                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf %lf", &t.chunk, &t.waves_per_cu, &t.threshold,
+                                               &t.kernel_ms, &t.default_ms) >= 4) {
                     std::fclose(f);
                     t.from_cache = 1;
                     for (int i = 0; i < n; ++i) {
@@ -1362,7 +1362,12 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         ms = res[0]->kernel_ms;
         return MCRT_OK;
     };
-    mcrt_tuning cur{256, 16, n == 1 ? 16 : 24, 0.0, 0};
+    // start from the library's own defaults (sims[0]'s options; chunk 0 = the
+    // automatic chunk), so the search can only keep or beat them
+    const mcrt_options &o0 = sims[0]->opt;
+    const mcrt_tuning dflt{o0.chunk, o0.waves_per_cu > 0 ? o0.waves_per_cu : 16,
+                           o0.threshold > 0 ? o0.threshold : (n == 1 ? 16 : 24), 0.0, 0, 0.0};
+    mcrt_tuning cur = dflt;
     double ms = 0.0;
     int rc = trial(cur, ms); // warm-up
     if (!rc) rc = trial(cur, ms);
@@ -1373,14 +1378,14 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     cur.kernel_ms = ms;
     // batches favour large chunks (a wave drains when its next chunk belongs
     // to another model)
-    const int chunks_single[] = {32, 64, 128, 256, 512, 1024, 2048};
-    const int chunks_batch[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+    const int chunks_single[] = {0, 32, 64, 128, 256, 512, 1024, 2048};
+    const int chunks_batch[] = {0, 256, 512, 1024, 2048, 4096, 8192, 16384};
     const int *chunks = n == 1 ? chunks_single : chunks_batch;
     const int thresholds[] = {8, 16, 24, 32, 48};
     const int waves[] = {8, 12, 16};
     for (int pass = 0; pass < 3 && !rc; ++pass) {
         const int *vals = pass == 0 ? chunks : pass == 1 ? thresholds : waves;
-        int nv = pass == 0 ? 7 : pass == 1 ? 5 : 3;
+        int nv = pass == 0 ? 8 : pass == 1 ? 5 : 3;
         for (int k = 0; k < nv; ++k) {
             mcrt_tuning t = cur;
             if (pass == 0) t.chunk = vals[k];
@@ -1395,6 +1400,32 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
             }
         }
     }
+    // confirmation: the pick and the defaults twice more each, alternating;
+    // the pick is kept only if its best time beats the defaults' best time
+    double best_pick = cur.kernel_ms, best_dflt = ms;
+    {
+        double m = 0.0;
+        best_dflt = 1e300;
+        for (int r = 0; r < 2 && !rc; ++r) {
+            rc = trial(dflt, m);
+            if (!rc) best_dflt = std::min(best_dflt, m);
+            if (!rc && (cur.chunk != dflt.chunk || cur.threshold != dflt.threshold ||
+                        cur.waves_per_cu != dflt.waves_per_cu)) {
+                rc = trial(cur, m);
+                if (!rc) best_pick = std::min(best_pick, m);
+            }
+        }
+        if (cur.chunk == dflt.chunk && cur.threshold == dflt.threshold && cur.waves_per_cu == dflt.waves_per_cu)
+            best_pick = std::min(best_pick, best_dflt);
+    }
+    if (!rc) {
+        if (best_pick >= best_dflt) {
+            cur = dflt;
+            best_pick = best_dflt;
+        }
+        cur.kernel_ms = best_pick;
+        cur.default_ms = best_dflt;
+    }
     cleanup();
     if (rc) return rc;
     for (int i = 0; i < n; ++i) {
@@ -1406,7 +1437,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     if (cache_path) {
         std::FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s|%d %d %d %.6f\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold, cur.kernel_ms);
+            std::fprintf(f, "%s|%d %d %d %.6f %.6f\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold,
+                         cur.kernel_ms, cur.default_ms);
             std::fclose(f);
         }
     }

@@ -75,7 +75,7 @@ STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("threshold", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+                ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32), ("default_ms", ctypes.c_double)]
 
 
 class MlpDesc(ctypes.Structure):
@@ -701,7 +701,7 @@ def autotune(sims: Sequence["Sim"], trial_packets: Sequence[int], seed: int = 0,
     _check(lib().mcrt_autotune(_handles(sims), n, tp, int(seed),
                                cache_path.encode() if cache_path else None, ctypes.byref(t)))
     return {"chunk": t.chunk, "waves_per_cu": t.waves_per_cu, "threshold": t.threshold,
-            "kernel_ms": t.kernel_ms, "from_cache": bool(t.from_cache)}
+            "kernel_ms": t.kernel_ms, "default_ms": t.default_ms, "from_cache": bool(t.from_cache)}
 
 
 def run_scene(scene, n_per_lambda: int, seed: int = 0, precision: int = FP32, first_id: int = 0,

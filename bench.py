@@ -537,7 +537,9 @@ def main():
                    waves_per_cu=args.waves_per_cu or None, threshold=args.threshold or None,
                    brick=brick, top_level=args.top_level if args.top_level >= 0 else None)
     if args.autotune:
-        t = mcrt.autotune([sim], [max(1, min(N, B) // 20)], seed=0,
+        # trials of one full step: a shorter launch is dominated by its tail
+        # (the longest packet histories), whose best queue differs
+        t = mcrt.autotune([sim], [min(N, B)], seed=0,
                           cache_path=os.path.join(ROOT, "_build", "tune_cache.txt"))
         print(f"[bench] autotune {t}", file=sys.stderr, flush=True)
     res = sim.new_result()

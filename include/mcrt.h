@@ -97,6 +97,10 @@ typedef struct {
                               MCRT_QUEUE_PAIRED.  A model's random streams are keyed by its
                               position in the caller's list, so no order changes a result,
                               only the launch's tail (Section 7.4, Fig. 14) */
+    int32_t chunk_shift;   /* the automatic chunk (chunk = 0) times 2^chunk_shift, in
+                              -6 .. 6; default 0.  The automatic chunk scales with the
+                              launch, so a shift tuned on a short trial carries over to
+                              the full launch */
 } mcrt_options;
 
 /* Batch queue orders (Section 5.2 assigners; Section 7.4 load-balance lesson). */
@@ -255,13 +259,16 @@ typedef struct {
     double kernel_ms;     /* trial time of this setting (output of the tuner) */
     int32_t from_cache;   /* 1 if the tuner found the setting in its cache */
     double default_ms;    /* trial time of the library's defaults (output of the tuner) */
+    int32_t chunk_shift;  /* with chunk = 0: the automatic chunk times 2^chunk_shift (-6 .. 6) */
 } mcrt_tuning;
 
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
 
 /* Autotuner: coordinate search, starting from sims[0]'s options (the
- * library's defaults unless set), over chunk ({auto, 32..2048} for one sim,
- * {auto, 256..16384} for a batch), threshold {8..48} and waves per CU
+ * library's defaults unless set), over the chunk as a multiple of the
+ * automatic chunk (chunk = 0, chunk_shift -3 .. 3: the automatic chunk
+ * scales with the launch, so a setting tuned on a short trial keeps its
+ * shape in the full launch), threshold {8..48} and waves per CU
  * {8, 12, 16} with trial runs of trial_packets[i] packets per wavelength of
  * each sim (one sim: the single-model kernel; several: the batched kernel),
  * keeping the fastest; the pick and the defaults are then timed twice more

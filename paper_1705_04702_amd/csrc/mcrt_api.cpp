@@ -212,6 +212,13 @@ struct mcrt_result {
     unsigned long long seen_capped = 0, seen_nonfinite = 0;
 };
 
+// The automatic chunk times 2^shift (at least 1, at most 2^24 packets).
+static uint64_t shifted_chunk(uint64_t c, int shift)
+{
+    c = shift >= 0 ? c << shift : c >> (-shift);
+    return c < 1 ? 1 : (c > (uint64_t(1) << 24) ? (uint64_t(1) << 24) : c);
+}
+
 // Codes after which a launch's results are still there to use.
 static inline bool soft_code(int rc) { return rc == MCRT_ELIMIT || rc == MCRT_ENONFINITE; }
 
@@ -248,6 +255,7 @@ void mcrt_options_default(mcrt_options *opt)
     opt->top_level = -1;
     opt->brick[0] = opt->brick[1] = opt->brick[2] = -1;
     opt->queue_order = MCRT_QUEUE_PAIRED;
+    opt->chunk_shift = 0;
 }
 
 int mcrt_context_create(int device, void *stream, mcrt_context **out)
@@ -531,7 +539,8 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         return fail(MCRT_EINVAL, "sim_create: unknown precision");
     if (!(o.w_min >= 0.0) || !(o.tau_peel_max > 0.0) || o.event_cap < 1)
         return fail(MCRT_EINVAL, "sim_create: w_min >= 0, tau_peel_max > 0, event_cap >= 1 required");
-    if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64)
+    if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64 ||
+        o.chunk_shift < -6 || o.chunk_shift > 6)
         return fail(MCRT_EINVAL, "sim_create: tuning values out of range");
     if (o.queue_order != MCRT_QUEUE_COST && o.queue_order != MCRT_QUEUE_CALLER && o.queue_order != MCRT_QUEUE_PAIRED)
         return fail(MCRT_EINVAL, "sim_create: unknown queue order");
@@ -785,7 +794,7 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
     // persistent wave gets work (never below 32)
     uint64_t auto_chunk = a.total / waves;
     auto_chunk = auto_chunk < 32 ? 32 : (auto_chunk > 256 ? 256 : auto_chunk);
-    a.chunk = (uint32_t)(s->opt.chunk > 0 ? (uint64_t)s->opt.chunk : auto_chunk);
+    a.chunk = (uint32_t)(s->opt.chunk > 0 ? (uint64_t)s->opt.chunk : shifted_chunk(auto_chunk, s->opt.chunk_shift));
     a.threshold = s->opt.threshold > 0 ? s->opt.threshold : 16;
     a.counter = scratch ? (unsigned long long *)scratch : r->d_counter;
     a.energy = r->d_energy;
@@ -1133,7 +1142,8 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     const int wpc0 = s0->opt.waves_per_cu > 0 ? s0->opt.waves_per_cu : 16;
     uint64_t auto_chunk = total_packets / (16ull * (uint64_t)s0->ctx->n_cu * (uint64_t)wpc0);
     auto_chunk = auto_chunk < 256 ? 256 : (auto_chunk > 16384 ? 16384 : auto_chunk);
-    const uint32_t chunk = (uint32_t)(s0->opt.chunk > 0 ? (uint64_t)s0->opt.chunk : auto_chunk);
+    const uint32_t chunk =
+        (uint32_t)(s0->opt.chunk > 0 ? (uint64_t)s0->opt.chunk : shifted_chunk(auto_chunk, s0->opt.chunk_shift));
     // Queue order: by estimated cost (packets x wavelengths x cells along the
     // axes) the most and least expensive alternating (default: on a batch of
     // 256 uneven models 1.5 % faster than longest-processing-time order and
@@ -1284,9 +1294,11 @@ int mcrt_batch_run_into(mcrt_sim *const *sims, int32_t n, const uint64_t *n_per_
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t)
 {
     if (!sim || !t) return fail(MCRT_EINVAL, "sim_set_tuning: NULL argument");
-    if (t->chunk < 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64)
+    if (t->chunk < 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64 ||
+        t->chunk_shift < -6 || t->chunk_shift > 6)
         return fail(MCRT_EINVAL, "sim_set_tuning: values out of range");
     sim->opt.chunk = t->chunk;
+    sim->opt.chunk_shift = t->chunk_shift;
     sim->opt.waves_per_cu = t->waves_per_cu;
     sim->opt.threshold = t->threshold;
     return MCRT_OK;
@@ -1324,8 +1336,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
                 if (!bar) continue;
                 *bar = 0;
                 mcrt_tuning t{};
-                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf %lf", &t.chunk, &t.waves_per_cu, &t.threshold,
-                                               &t.kernel_ms, &t.default_ms) >= 4) {
+                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf %lf %d", &t.chunk, &t.waves_per_cu,
+                                               &t.threshold, &t.kernel_ms, &t.default_ms, &t.chunk_shift) >= 4) {
                     std::fclose(f);
                     t.from_cache = 1;
                     for (int i = 0; i < n; ++i) {
@@ -1366,7 +1378,7 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     // automatic chunk), so the search can only keep or beat them
     const mcrt_options &o0 = sims[0]->opt;
     const mcrt_tuning dflt{o0.chunk, o0.waves_per_cu > 0 ? o0.waves_per_cu : 16,
-                           o0.threshold > 0 ? o0.threshold : (n == 1 ? 16 : 24), 0.0, 0, 0.0};
+                           o0.threshold > 0 ? o0.threshold : (n == 1 ? 16 : 24), 0.0, 0, 0.0, o0.chunk_shift};
     mcrt_tuning cur = dflt;
     double ms = 0.0;
     int rc = trial(cur, ms); // warm-up
@@ -1376,22 +1388,29 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         return rc;
     }
     cur.kernel_ms = ms;
-    // batches favour large chunks (a wave drains when its next chunk belongs
-    // to another model)
-    const int chunks_single[] = {0, 32, 64, 128, 256, 512, 1024, 2048};
-    const int chunks_batch[] = {0, 256, 512, 1024, 2048, 4096, 8192, 16384};
-    const int *chunks = n == 1 ? chunks_single : chunks_batch;
+    // the chunk as a multiple of the automatic chunk, which scales with the
+    // launch: a short trial then has the full launch's chunks per wave
+    const int shifts[] = {-3, -2, -1, 0, 1, 2, 3};
     const int thresholds[] = {8, 16, 24, 32, 48};
     const int waves[] = {8, 12, 16};
+    auto same = [](const mcrt_tuning &x, const mcrt_tuning &y) {
+        return x.chunk == y.chunk && x.chunk_shift == y.chunk_shift && x.threshold == y.threshold &&
+               x.waves_per_cu == y.waves_per_cu;
+    };
     for (int pass = 0; pass < 3 && !rc; ++pass) {
-        const int *vals = pass == 0 ? chunks : pass == 1 ? thresholds : waves;
-        int nv = pass == 0 ? 8 : pass == 1 ? 5 : 3;
+        const int *vals = pass == 0 ? shifts : pass == 1 ? thresholds : waves;
+        int nv = pass == 0 ? 7 : pass == 1 ? 5 : 3;
         for (int k = 0; k < nv; ++k) {
             mcrt_tuning t = cur;
-            if (pass == 0) t.chunk = vals[k];
-            else if (pass == 1) t.threshold = vals[k];
-            else t.waves_per_cu = vals[k];
-            if (t.chunk == cur.chunk && t.threshold == cur.threshold && t.waves_per_cu == cur.waves_per_cu) continue;
+            if (pass == 0) {
+                t.chunk = 0;
+                t.chunk_shift = vals[k];
+            } else if (pass == 1) {
+                t.threshold = vals[k];
+            } else {
+                t.waves_per_cu = vals[k];
+            }
+            if (same(t, cur)) continue;
             rc = trial(t, ms);
             if (rc) break;
             if (ms < cur.kernel_ms) {
@@ -1409,14 +1428,12 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
         for (int r = 0; r < 2 && !rc; ++r) {
             rc = trial(dflt, m);
             if (!rc) best_dflt = std::min(best_dflt, m);
-            if (!rc && (cur.chunk != dflt.chunk || cur.threshold != dflt.threshold ||
-                        cur.waves_per_cu != dflt.waves_per_cu)) {
+            if (!rc && !same(cur, dflt)) {
                 rc = trial(cur, m);
                 if (!rc) best_pick = std::min(best_pick, m);
             }
         }
-        if (cur.chunk == dflt.chunk && cur.threshold == dflt.threshold && cur.waves_per_cu == dflt.waves_per_cu)
-            best_pick = std::min(best_pick, best_dflt);
+        if (same(cur, dflt)) best_pick = std::min(best_pick, best_dflt);
     }
     if (!rc) {
         if (best_pick >= best_dflt) {
@@ -1437,8 +1454,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     if (cache_path) {
         std::FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s|%d %d %d %.6f %.6f\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold,
-                         cur.kernel_ms, cur.default_ms);
+            std::fprintf(f, "%s|%d %d %d %.6f %.6f %d\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold,
+                         cur.kernel_ms, cur.default_ms, cur.chunk_shift);
             std::fclose(f);
         }
     }

@@ -63,6 +63,7 @@ class Options(ctypes.Structure):
         ("top_level", ctypes.c_int32),
         ("brick", ctypes.c_int32 * 3),
         ("queue_order", ctypes.c_int32),
+        ("chunk_shift", ctypes.c_int32),
     ]
 
 
@@ -75,7 +76,8 @@ STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("threshold", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32), ("default_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32), ("default_ms", ctypes.c_double),
+                ("chunk_shift", ctypes.c_int32)]
 
 
 class MlpDesc(ctypes.Structure):
@@ -700,8 +702,9 @@ def autotune(sims: Sequence["Sim"], trial_packets: Sequence[int], seed: int = 0,
     t = Tuning()
     _check(lib().mcrt_autotune(_handles(sims), n, tp, int(seed),
                                cache_path.encode() if cache_path else None, ctypes.byref(t)))
-    return {"chunk": t.chunk, "waves_per_cu": t.waves_per_cu, "threshold": t.threshold,
-            "kernel_ms": t.kernel_ms, "default_ms": t.default_ms, "from_cache": bool(t.from_cache)}
+    return {"chunk": t.chunk, "chunk_shift": t.chunk_shift, "waves_per_cu": t.waves_per_cu,
+            "threshold": t.threshold, "kernel_ms": t.kernel_ms, "default_ms": t.default_ms,
+            "from_cache": bool(t.from_cache)}
 
 
 def run_scene(scene, n_per_lambda: int, seed: int = 0, precision: int = FP32, first_id: int = 0,

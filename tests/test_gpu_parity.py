@@ -354,3 +354,26 @@ def test_axis_aligned_instruments_fp64(ctx):
     assert o["stats"]["peel_dropped"] > 0
     g = gpu_run(ctx, sc, N, seed=13)
     assert_fp64_parity(g, o)
+
+
+@pytest.mark.parametrize("cut", [float("inf"), 0.7])
+def test_octree_axis_aligned_instruments_fp64(ctx, cut):
+    """Octree grids: peel-offs along the six grid axes read the lattice
+    column maps (two reads, no march) beside an oblique instrument that
+    marches; a random octree with random densities and a source inside, the
+    same with the source outside the grid, and a small clumpy torus: FP64
+    parity per pixel with the oracle's leaf-by-leaf marches, drops at a tau
+    cut included."""
+    from test_lanesim import AXES, _random_octree_scene
+    for sc in (_random_octree_scene(5, (0.137, -0.421, 0.25)), _random_octree_scene(6, (1.7, 0.3, -0.2)),
+               scenes.torus(5, 4, 2, 16, n_clumps=25, tau_eq=8.0)):
+        small = sc.box[3] < 5
+        sc.instruments = [scenes.Instrument(i, a, 100.0 if small else 1.0e4, (2.2, 2.2) if small else (30.0, 30.0),
+                                            (16, 16)) for i, a in AXES]
+        sc.tau_peel_max = cut
+        o = oracle.run(sc, 700, seed=14)
+        if cut < 1e30:
+            assert o["stats"]["peel_dropped"] > 0
+        g = gpu_run(ctx, sc, 700, seed=14)
+        assert_fp64_parity(g, o)
+        assert 0 < g["stats"]["peel_cells"] < o["stats"]["peel_cells"] / 3

@@ -377,3 +377,56 @@ def test_octree_axis_aligned_instruments_fp64(ctx, cut):
         g = gpu_run(ctx, sc, 700, seed=14)
         assert_fp64_parity(g, o)
         assert 0 < g["stats"]["peel_cells"] < o["stats"]["peel_cells"] / 3
+
+
+def _deep_octree_scene(depth=12):
+    """An octree refined to depth 12 around two points (a few random coarse
+    refinements besides): leaves from level 1 to 12, so the walk chains
+    blocks three deep below its top table; deeper than the lattice column
+    maps go (10), so the axis-aligned instruments march."""
+    pts = np.array([[0.6173, 0.3391, 0.5527], [0.2468, 0.7113, 0.4029]])
+    rng = np.random.default_rng(21)
+
+    def refine(level, ix, iy, iz):
+        n = 1 << level
+        hit = np.zeros(ix.shape, bool)
+        for p in pts:
+            c = np.floor(p * n).astype(np.int64)
+            hit |= (ix == c[0]) & (iy == c[1]) & (iz == c[2])
+        return hit | ((level < 3) & (rng.random(ix.shape[0]) < 0.5)) | (level == 0)
+
+    fc, leaves, D = scenes.octree_from_levels(refine, depth)
+    nl = leaves[0].shape[0]
+    dens = np.random.default_rng(22).uniform(0.2, 3.0, nl).astype(np.float32)
+    src = tuple(-1.0 + 2.0 * pts[0] + 1e-4)  # inside the deepest leaves
+    sc = scenes.Scene(grid_type="octree", box=(-1.0, -1.0, -1.0, 1.0, 1.0, 1.0), first_child=fc, density=dens,
+                      lambdas=np.array([0.55, 3.0]), kappa=np.array([1.2, 0.3]), albedo=np.array([0.6, 0.4]),
+                      hg_g=np.array([0.3, 0.0]), lum=np.array([1.0, 0.5]), source="point_iso", src_pos=src,
+                      instruments=[scenes.Instrument(i, a, 100.0, (2.2, 2.2), (32, 32))
+                                   for i, a in ((90, 0), (0, 0), (50, 20))], name="deep_octree12")
+    return sc, D
+
+
+def test_deep_octree_fp64_and_fp32(ctx):
+    sc, D = _deep_octree_scene()
+    assert D == 12
+    o = oracle.run(sc, 2000, seed=3)
+    g = gpu_run(ctx, sc, 2000, seed=3)
+    assert_fp64_parity(g, o)
+    assert g["stats"]["guard"] == 0 and g["stats"]["peel_cells"] == o["stats"]["peel_cells"]
+    f = gpu_run(ctx, sc, 20000, seed=3, precision=mcrt.FP32)
+    e = f["energy"]
+    assert abs(e[0] - e[1] - e[2] - e[3]) / e[0] < 1e-5 and f["stats"]["guard"] == 0
+
+
+def test_largest_packet_ids_fp64(ctx):
+    """The largest run the boundary accepts, 2^32 packets per wavelength:
+    its last ids (up to 2^32 - 1, the full width of the stream counter's
+    packet word) against the oracle."""
+    sc = scenes.disk((16, 16, 8), 2, 24)
+    N = 1 << 32
+    first, count = N - 257, 257
+    o = oracle.run(sc, N, seed=5, first_id=first, count=count)
+    g = gpu_run(ctx, sc, N, seed=5, first_id=first, count=count)
+    assert g["stats"]["packets"] == 2 * count
+    assert_fp64_parity(g, o)

@@ -3,16 +3,25 @@
 // The network maps the 9 features of an emission or scattering event to the
 // 40 parameters of an 8-lobe von Mises-Fisher mixture: 9 -> 64 -> 64 -> 40
 // with ReLU, bfloat16 weights, inputs and hidden activations, FP32 sums.
-// Every layer runs transposed, Z^T = W^T X^T, on 16 x 16 x 16 bf16 MFMA
-// tiles with the samples along the tile columns: the accumulator a lane holds
-// for one 16-row output tile is then exactly the B operand that the next
-// layer needs for the matching 16-deep slice of its reduction, so the hidden
-// activations never leave the registers.
+// Every layer runs transposed, Z^T = W^T X^T, on bf16 MFMA tiles with the
+// samples along the tile columns: the accumulator a lane holds for one 16-row
+// output tile is then exactly the B operand that the next layer needs for the
+// matching 16-deep slice of its reduction, so the hidden activations never
+// leave the registers.
 //
 // MFMA 16x16x16 operand layout (lane l of a 64-lane wave, i = 0..3):
 //   A[m][k]: m = l % 16, k = 4 (l / 16) + i
 //   B[k][n]: k = 4 (l / 16) + i, n = l % 16
 //   C[m][n]: m = 4 (l / 16) + i, n = l % 16
+//
+// The 64-deep reductions (layers 2 and 3, and the backward product through
+// W2) run on CDNA4's 16 x 16 x 32 bf16 MFMA, two 16-deep slices 2j, 2j + 1 per
+// instruction: a lane passes the concatenation of its two 16x16x16 operands
+// (eight values) as A and as B.  The instruction's reduction then runs over a
+// permutation of the 32 indices (element i of lane group l / 16 is index
+// 16 (2j + i / 4) + 4 (l / 16) + i % 4 in both operands), which leaves the sum
+// unchanged, so the fragments and the C -> B chaining are those of the
+// 16-deep form.  Layer 1 (9 features, padded to 16) stays on 16x16x16.
 //
 // Weights live in "fragment order": fragment F holds, for each lane, the four
 // bf16 values of that lane's A operand, so one 8-byte load per lane fetches a
@@ -31,6 +40,8 @@
 namespace mcrt {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8_bits __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFragFwd = 32;                // forward fragments
@@ -51,6 +62,20 @@ __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// C += A B over two 16-deep slices at once: A = (a0, a1), B = (b0, b1), where
+// (a0, b0) and (a1, b1) are the operands of the two slices in the 16x16x16
+// layout.  A chain of MFMAs on one accumulator keeps to one form: the
+// compiler issues a 16x16x16 that takes as C the accumulator a 16x16x32 has
+// just written directly behind it, with no wait, and the sum then misses
+// part of the first product.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c)
+{
+    const bf16x8_bits a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8_bits b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
 }
 
 __device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d)
@@ -125,14 +150,18 @@ __device__ __forceinline__ void mlp_forward16(const bf16x4 *Wf, const float *bia
     for (int t = 0; t < 4; ++t) {
         f32x4 c = bias4(bias, 64 + 16 * t, lane);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) c = mfma16(Wf[(4 + 4 * t + kk) * 64 + lane], h1[kk], c);
+        for (int j = 0; j < 2; ++j)
+            c = mfma32(Wf[(4 + 4 * t + 2 * j) * 64 + lane], Wf[(5 + 4 * t + 2 * j) * 64 + lane], h1[2 * j],
+                       h1[2 * j + 1], c);
         h2[t] = relu_bf16(c);
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         f32x4 c = bias4(bias, 128 + 16 * t, lane);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) c = mfma16(Wf[(20 + 4 * t + kk) * 64 + lane], h2[kk], c);
+        for (int j = 0; j < 2; ++j)
+            c = mfma32(Wf[(20 + 4 * t + 2 * j) * 64 + lane], Wf[(21 + 4 * t + 2 * j) * 64 + lane], h2[2 * j],
+                       h2[2 * j + 1], c);
         o[t] = c;
     }
     if constexpr (KEEP) {

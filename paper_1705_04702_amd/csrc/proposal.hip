@@ -308,11 +308,17 @@ __global__ void __launch_bounds__(64) grad_kernel(GradArgs g)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int ko = 0; ko < 3; ++ko) {
-                    bf16x4 A = s_wf[(32 + 3 * t + ko) * 64 + lane];
-                    c = mfma16(A, lds4(s_dos_hi + (16 * sb + r16) * kSO + 16 * ko + q4), c);
-                    c = mfma16(A, lds4(s_dos_lo + (16 * sb + r16) * kSO + 16 * ko + q4), c);
+                {
+                    // output slices 0 and 1, high then low parts, on two 32-deep MFMAs; slice 2 (outputs
+                    // 32..47) on a third that pairs the slice with itself: A = (A2, A2), B = (high, low)
+                    // sums A2 high + A2 low.  One MFMA form per accumulator chain (see mfma32).
+                    const bf16x4 A0 = s_wf[(32 + 3 * t) * 64 + lane], A1 = s_wf[(33 + 3 * t) * 64 + lane];
+                    const bf16x4 A2 = s_wf[(34 + 3 * t) * 64 + lane];
+                    const uint16_t *hi = s_dos_hi + (16 * sb + r16) * kSO + q4;
+                    const uint16_t *lo = s_dos_lo + (16 * sb + r16) * kSO + q4;
+                    c = mfma32(A0, A1, lds4(hi), lds4(hi + 16), c);
+                    c = mfma32(A0, A1, lds4(lo), lds4(lo + 16), c);
+                    c = mfma32(A2, A2, lds4(hi + 32), lds4(lo + 32), c);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -329,10 +335,11 @@ __global__ void __launch_bounds__(64) grad_kernel(GradArgs g)
             for (int t = 0; t < 4; ++t) {
                 f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    bf16x4 A = s_wf[(44 + 4 * t + kk) * 64 + lane];
-                    c = mfma16(A, z2hi[kk], c);
-                    c = mfma16(A, z2lo[kk], c);
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x4 A0 = s_wf[(44 + 4 * t + 2 * j) * 64 + lane];
+                    const bf16x4 A1 = s_wf[(45 + 4 * t + 2 * j) * 64 + lane];
+                    c = mfma32(A0, A1, z2hi[2 * j], z2hi[2 * j + 1], c);
+                    c = mfma32(A0, A1, z2lo[2 * j], z2lo[2 * j + 1], c);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)

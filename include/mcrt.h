@@ -36,6 +36,20 @@
  *  - Units are arbitrary but consistent: lengths (grid box, distances, field
  *    of view) in one unit, kappa is extinction per unit density per unit
  *    length, luminosities per wavelength bin.
+ *  - Run log (the paper's per-phase timing, Section 7, as one record per
+ *    launch): with the environment variable MCRT_LOG set to a positive
+ *    integer, every timed transport launch (mcrt_run_into, mcrt_run_range,
+ *    mcrt_run, mcrt_batch_run_into, mcrt_run_dust_into and the dust cycles,
+ *    mcrt_proposal_collect) appends one JSON line to the file named by
+ *    MCRT_LOG_FILE, else to stderr: the entry point, the scene's shape
+ *    (grid kind, cells, wavelengths, instruments; summed over a batch's
+ *    models), precision, the id range, the counters of mcrt_stats that THIS
+ *    launch added, the kernel time, and packets/s, deposits/s (propagation
+ *    cells + pixel additions), the algorithmic HBM bytes (12 per
+ *    propagation cell, 4 per interaction-search or peel-off cell, 4 (FP32)
+ *    or 8 (FP64) per pixel addition), their rate in GB/s and its fraction of
+ *    8 TB/s, and the return code.  Both variables are read at every launch.
+ *    Autotuner trials and the untimed mcrt_run_into_noalloc are not logged.
  */
 #ifndef MCRT_H
 #define MCRT_H

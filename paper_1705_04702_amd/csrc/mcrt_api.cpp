@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -207,9 +208,9 @@ struct mcrt_result {
     unsigned long long *d_stats = nullptr;   // [kNumStats]
     unsigned long long *d_counter = nullptr; // queue position
     double kernel_ms = 0.0;
-    // the cumulative capped / non-finite counts after the last launch into
-    // this result, so that a launch reports only what it added itself
-    unsigned long long seen_capped = 0, seen_nonfinite = 0;
+    // the cumulative counters after the last launch into this result, so
+    // that a launch reports (return code, run log) only what it added itself
+    unsigned long long seen[kNumStats] = {};
 };
 
 // The automatic chunk times 2^shift (at least 1, at most 2^24 packets).
@@ -222,20 +223,107 @@ static uint64_t shifted_chunk(uint64_t c, int shift)
 // Codes after which a launch's results are still there to use.
 static inline bool soft_code(int rc) { return rc == MCRT_ELIMIT || rc == MCRT_ENONFINITE; }
 
-// The return code of a launch into r from the stats it left (stats[7]
-// capped, stats[9] non-finite): MCRT_ENONFINITE or MCRT_ELIMIT when this
-// launch raised the count, else MCRT_OK.
-static int launch_outcome(mcrt_result *r, const unsigned long long *stats)
+// The return code of a launch into r from the cumulative stats it left
+// (stats[7] capped, stats[9] non-finite): MCRT_ENONFINITE or MCRT_ELIMIT when
+// this launch raised the count, else MCRT_OK.  delta (optional) receives what
+// the launch added to every counter.
+static int launch_outcome(mcrt_result *r, const unsigned long long *stats, unsigned long long *delta = nullptr)
 {
-    const bool capped = stats[7] > r->seen_capped, nonfinite = stats[9] > r->seen_nonfinite;
-    r->seen_capped = stats[7];
-    r->seen_nonfinite = stats[9];
+    const bool capped = stats[7] > r->seen[7], nonfinite = stats[9] > r->seen[9];
+    for (int k = 0; k < kNumStats; ++k) {
+        if (delta) delta[k] = stats[k] - r->seen[k];
+        r->seen[k] = stats[k];
+    }
     if (nonfinite)
         return fail(MCRT_ENONFINITE, "packets whose luminosity became NaN or infinite were ended (see "
                                      "stats.nonfinite); the other packets' results are valid");
     if (capped) return fail(MCRT_ELIMIT, "packets hit the event cap (results valid; see stats.capped)");
     return MCRT_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Run log.  With the environment variable MCRT_LOG set to a positive integer,
+// every timed transport launch appends one JSON line to the file that
+// MCRT_LOG_FILE names (else to stderr): what ran, the counters the launch
+// added, its kernel time, and the rates derived from them -- packets/s,
+// deposits/s (propagation cells plus pixel additions) and the algorithmic
+// HBM bytes (per propagation cell a 4-byte density read and a table deposit
+// of 8 bytes, per interaction-search or peel-off cell a 4-byte density read,
+// per pixel addition the image element) over the kernel time, also as a
+// fraction of 8 TB/s.  The variables are read at every launch.  Autotuner
+// trials and allocation-free launches (untimed) are not logged.
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_log_mu;
+thread_local int g_log_muted = 0;
+constexpr double kHbmPeakGBs = 8000.0;
+
+struct Counters {
+    unsigned long long v[kNumStats];
+};
+
+int log_level()
+{
+    const char *s = std::getenv("MCRT_LOG");
+    return s ? std::atoi(s) : 0;
+}
+
+struct LogMute {
+    LogMute() { ++g_log_muted; }
+    ~LogMute() { --g_log_muted; }
+};
+
+// One launch's line.  sims/deltas: the launch's models (one, except for a
+// batch) and the counters each added; fields that differ between a batch's
+// models are summed (cells, wavelengths, instruments, counters).
+void log_launch(const char *entry, mcrt_sim *const *sims, int n, const Counters *deltas,
+                uint64_t n_per_lambda, uint64_t first_id, uint64_t count, uint64_t seed, double kernel_ms, int rc)
+{
+    if (g_log_muted || log_level() <= 0) return;
+    const mcrt_sim *s0 = sims[0];
+    const bool fp32 = s0->opt.precision == MCRT_FP32;
+    unsigned long long d[kNumStats] = {};
+    long long cells = 0;
+    int n_lambda = 0, n_ins = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < kNumStats; ++k) d[k] += deltas[i].v[k];
+        cells += (long long)sims[i]->medium->grid->n_cells;
+        n_lambda += sims[i]->medium->n_lambda;
+        n_ins += sims[i]->n_ins;
+    }
+    const double bytes = 12.0 * (double)d[2] + 4.0 * (double)(d[3] + d[4]) + (fp32 ? 4.0 : 8.0) * (double)d[5];
+    const double sec = kernel_ms * 1e-3;
+    const double per_s = sec > 0.0 ? 1.0 / sec : 0.0;
+    char buf[2048];
+    snprintf(buf, sizeof buf,
+             "{\"mcrt\":\"launch\",\"entry\":\"%s\",\"device\":%d,\"grid\":\"%s\",\"models\":%d,"
+             "\"cells\":%lld,\"n_lambda\":%d,\"instruments\":%d,\"precision\":\"%s\",\"learned\":%s,"
+             "\"n_per_lambda\":%llu,\"first_id\":%llu,\"count\":%llu,\"seed\":%llu,"
+             "\"packets\":%llu,\"events\":%llu,\"prop_cells\":%llu,\"locate_cells\":%llu,"
+             "\"peel_cells\":%llu,\"peel_adds\":%llu,\"peel_dropped\":%llu,\"capped\":%llu,"
+             "\"guard\":%llu,\"nonfinite\":%llu,\"kernel_ms\":%.9g,\"packets_per_s\":%.9g,"
+             "\"deposits_per_s\":%.9g,\"algorithmic_bytes\":%.9g,\"achieved_GBps\":%.9g,"
+             "\"hbm_frac\":%.9g,\"rc\":%d}\n",
+             entry, s0->ctx->device, s0->medium->grid->type == kOctree ? "octree" : "cartesian", n, cells, n_lambda,
+             n_ins, fp32 ? "fp32" : "fp64", s0->prop ? "true" : "false", (unsigned long long)n_per_lambda,
+             (unsigned long long)first_id, (unsigned long long)count, (unsigned long long)seed, d[0], d[1], d[2],
+             d[3], d[4], d[5], d[6], d[7], d[8], d[9], kernel_ms, (double)d[0] * per_s,
+             (double)(d[2] + d[5]) * per_s, bytes, bytes * per_s * 1e-9, bytes * per_s * 1e-9 / kHbmPeakGBs, rc);
+    std::lock_guard<std::mutex> lock(g_log_mu);
+    const char *path = std::getenv("MCRT_LOG_FILE");
+    if (path && *path) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fputs(buf, f);
+            std::fclose(f);
+        }
+    } else {
+        std::fputs(buf, stderr);
+        std::fflush(stderr);
+    }
+}
+
+} // namespace
 
 // Definitions of the functions declared extern "C" in mcrt.h (they keep C
 // linkage from that declaration).
@@ -671,7 +759,7 @@ int mcrt_result_zero(mcrt_result *res)
     HIP_TRY(launch_fill_zero(res->d_stats, kNumStats * sizeof(unsigned long long), st));
     HIP_TRY(hipStreamSynchronize(st));
     res->kernel_ms = 0.0;
-    res->seen_capped = res->seen_nonfinite = 0;
+    std::fill(res->seen, res->seen + kNumStats, 0ull);
     return MCRT_OK;
 }
 
@@ -828,8 +916,13 @@ static int run_impl(mcrt_sim *s, uint64_t n_per_lambda, uint64_t first_id, uint6
         r->kernel_ms = ms;
     }
     unsigned long long stats[kNumStats];
+    Counters delta;
     HIP_TRY(hipMemcpy(stats, r->d_stats, sizeof(stats), hipMemcpyDeviceToHost));
-    return launch_outcome(r, stats);
+    const int rc = launch_outcome(r, stats, delta.v);
+    if (!scratch)
+        log_launch(hist ? "proposal_collect" : (dust ? "run_dust_into" : "run_into"), &s, 1, &delta, n_per_lambda,
+                   first_id, count, seed, r->kernel_ms, rc);
+    return rc;
 }
 
 namespace {
@@ -1252,13 +1345,18 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     int worst = MCRT_OK;
+    std::vector<Counters> deltas((size_t)n);
+    uint64_t requested = 0;
     for (int i = 0; i < n; ++i) {
         res[i]->kernel_ms = ms;
         unsigned long long stt[kNumStats];
         HIP_TRY(hipMemcpy(stt, res[i]->d_stats, sizeof(stt), hipMemcpyDeviceToHost));
-        const int oc = launch_outcome(res[i], stt);
+        const int oc = launch_outcome(res[i], stt, deltas[(size_t)i].v);
         if (oc == MCRT_ENONFINITE || (oc == MCRT_ELIMIT && worst == MCRT_OK)) worst = oc;
+        requested += npl[i] * (uint64_t)sims[i]->medium->n_lambda;
     }
+    // n_per_lambda and count of a batch line: the packets of all models
+    log_launch("batch_run_into", sims, n, deltas.data(), requested, 0, requested, seed, ms, worst);
     if (worst == MCRT_ENONFINITE)
         return fail(MCRT_ENONFINITE, "packets whose luminosity became NaN or infinite were ended (see "
                                      "stats.nonfinite); the other packets' results are valid");
@@ -1326,6 +1424,7 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
                   const char *cache_path, mcrt_tuning *best)
 {
     if (!sims || n <= 0 || !trial_packets || !best) return fail(MCRT_EINVAL, "autotune: NULL argument or n <= 0");
+    LogMute mute; // trial launches stay out of the run log
     const std::string key = tune_key(sims, n);
     if (cache_path) {
         std::FILE *f = std::fopen(cache_path, "r");

@@ -86,17 +86,16 @@ template <typename Real, int G>
 static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, uint64_t seed, ls_out *o)
 {
     View<Real, Real, G> v{};
-    std::vector<int32_t> node, top;
+    std::vector<int32_t> node;
+    std::vector<uint64_t> top, blocks;
     int depth = 0;
     if (s->grid_type == kOctree) {
         std::string err;
         depth = encode_octree(s->n_nodes, s->first_child, s->n_cells, node, err);
         if (depth < 0) return -2;
         v.top_level = s->top_level >= 0 ? (s->top_level < depth ? s->top_level : depth) : (depth < 7 ? depth : 7);
-        std::vector<int32_t> blocks;
-        if (!build_walk(node, depth, v.top_level, top, blocks, err)) return -2;
-        node.swap(blocks);
-        if (node.empty()) node.assign(1, 0);
+        if (!build_walk(node, depth, v.top_level, s->density, top, blocks, err)) return -2;
+        if (blocks.empty()) blocks.assign(1, 0);
         for (int a = 0; a < 3; ++a) v.n[a] = 1 << depth;
     } else {
         for (int a = 0; a < 3; ++a) v.n[a] = s->n[a];
@@ -126,8 +125,8 @@ static int run(const ls_scene *s, uint64_t npl, uint64_t first, uint64_t count, 
     } else {
         v.density = s->density;
     }
-    v.node = node.data();
-    v.top = top.data();
+    v.node = (const unsigned long long *)blocks.data();
+    v.top = (const unsigned long long *)top.data();
     v.n_cells = s->n_cells;
     v.n_lambda = s->n_lambda;
     std::vector<Optics<Real>> optics((size_t)s->n_lambda);

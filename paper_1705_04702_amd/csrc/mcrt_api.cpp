@@ -152,8 +152,8 @@ struct mcrt_sim {
     long long n_store = 0;                     // stored cells per wavelength slice
     // device copies of the scene
     float *d_density = nullptr;
-    int *d_node = nullptr;
-    int *d_top = nullptr;
+    unsigned long long *d_node = nullptr; // octree walk blocks (64-bit entries)
+    unsigned long long *d_top = nullptr;  // octree walk top table
     void *d_optics = nullptr; // Optics<Real>[n_lambda], rewritten per run
     void *d_optics_base = nullptr; // Optics<Real>[n_lambda] with L0 = 0 (allocation-free runs)
     double *d_lum = nullptr;       // source luminosity per wavelength, FP64 (allocation-free runs)
@@ -692,20 +692,19 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
         if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("density upload: ") + hipGetErrorString(e));
     }
     if (!rc && g->type == kOctree) {
-        std::vector<int32_t> node, top;
+        std::vector<int32_t> node;
         std::string err;
         int depth = encode_octree((int64_t)g->first_child.size(), g->first_child.data(), g->n_cells, node, err);
         s->depth = depth;
         s->top_level = o.top_level >= 0 ? std::min(o.top_level, depth) : std::min(depth, 7);
-        std::vector<int32_t> blocks;
-        if (!build_walk(node, depth, s->top_level, top, blocks, err)) rc = fail(MCRT_EINVAL, err);
-        node.swap(blocks); // the kernel walks the blocks
-        if (node.empty()) node.assign(1, 0);
-        if (!rc) rc = dev_alloc((void **)&s->d_node, node.size() * sizeof(int32_t));
-        if (!rc) rc = dev_alloc((void **)&s->d_top, top.size() * sizeof(int32_t));
+        std::vector<uint64_t> top, blocks;
+        if (!build_walk(node, depth, s->top_level, dens, top, blocks, err)) rc = fail(MCRT_EINVAL, err);
+        if (blocks.empty()) blocks.assign(1, 0);
+        if (!rc) rc = dev_alloc((void **)&s->d_node, blocks.size() * sizeof(uint64_t));
+        if (!rc) rc = dev_alloc((void **)&s->d_top, top.size() * sizeof(uint64_t));
         if (!rc) {
-            hipError_t e = hipMemcpy(s->d_node, node.data(), node.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(s->d_top, top.data(), top.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            hipError_t e = hipMemcpy(s->d_node, blocks.data(), blocks.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(s->d_top, top.data(), top.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
             if (e != hipSuccess) rc = fail(MCRT_EDEVICE, std::string("octree upload: ") + hipGetErrorString(e));
         }
     }

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -167,12 +168,22 @@ inline int encode_octree(int64_t n_nodes, const int32_t *first_child, int64_t n_
 // The leaf walk of the transport kernel.  A dense top table at level
 // top_level, then blocks of 64 entries that each cover the two levels below an
 // internal node (4 x 4 x 4 sub-cubes, index i + 4 j + 16 k): one dependent
-// load per two tree levels.  An entry is either a leaf, 1 << 31 | (level << 27)
-// | cell, or the index of the next block (below 2^25).  A leaf one level below
-// the node fills its 8 sub-cubes; a node one level above the deepest leaves
-// gets a block whose lower sub-cube bit is a copy (the walk reads it as 0).
-// Returns false (with a message) if the blocks would not fit 32-bit indices.
-inline uint32_t walk_leaf(int level, int32_t val) { return (1u << 31) | ((uint32_t)level << 27) | (uint32_t)(-val - 1); }
+// load per two tree levels.  An entry is 64 bits: its low word is either a
+// leaf, 1 << 31 | (level << 27) | cell, or the index of the next block (below
+// 2^25); a leaf's high word holds the bits of the leaf's FP32 density, so the
+// load that finds the leaf also brings its density (no load from a separate
+// density array, whose line would be one more request per step).  A leaf one
+// level below the node fills its 8 sub-cubes; a node one level above the
+// deepest leaves gets a block whose lower sub-cube bit is a copy (the walk
+// reads it as 0).  Returns false (with a message) if the blocks would not fit
+// 32-bit indices.
+inline uint64_t walk_leaf(int level, int32_t val, const float *density)
+{
+    const uint32_t cell = (uint32_t)(-val - 1);
+    uint32_t rho;
+    std::memcpy(&rho, density + cell, sizeof(rho));
+    return ((uint64_t)rho << 32) | (1u << 31) | ((uint32_t)level << 27) | cell;
+}
 
 // Position of a top-level cube in the top table: 4 x 4 x 4 tiles (the
 // device's top_index), linear below level 2.
@@ -184,8 +195,8 @@ inline int top_index_host(int x, int y, int z, int top_level)
     return (tile << 6) + ((z & 3) << 4) + ((y & 3) << 2) + (x & 3);
 }
 
-inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_level, std::vector<int32_t> &top,
-                       std::vector<int32_t> &blocks, std::string &err)
+inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_level, const float *density,
+                       std::vector<uint64_t> &top, std::vector<uint64_t> &blocks, std::string &err)
 {
     blocks.clear();
     // block of internal node nd at level L; returns its index
@@ -203,16 +214,16 @@ inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_leve
                     const int c1 = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
                     const int32_t m1 = node[(size_t)nd] + c1;
                     const int32_t e1 = node[(size_t)m1];
-                    uint32_t e;
+                    uint64_t e;
                     if (e1 < 0) {
-                        e = walk_leaf(level + 1, e1);
+                        e = walk_leaf(level + 1, e1, density);
                     } else {
                         const int c2 = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
                         const int32_t m2 = e1 + c2;
                         const int32_t e2 = node[(size_t)m2];
-                        e = e2 < 0 ? walk_leaf(level + 2, e2) : new_block(m2, level + 2);
+                        e = e2 < 0 ? walk_leaf(level + 2, e2, density) : new_block(m2, level + 2);
                     }
-                    blocks[b * 64 + (size_t)(i + 4 * j + 16 * k)] = (int32_t)e;
+                    blocks[b * 64 + (size_t)(i + 4 * j + 16 * k)] = e;
                 }
     };
     const int T = 1 << top_level;
@@ -230,14 +241,14 @@ inline bool build_walk(const std::vector<int32_t> &node, int depth, int top_leve
                     level++;
                 }
                 const int32_t val = node[(size_t)nd];
-                uint32_t e;
+                uint64_t e;
                 if (val < 0) {
-                    e = walk_leaf(level, val);
+                    e = walk_leaf(level, val, density);
                 } else {
                     if (block_of[(size_t)nd] < 0) block_of[(size_t)nd] = (int32_t)new_block(nd, level);
-                    e = (uint32_t)block_of[(size_t)nd];
+                    e = (uint64_t)(uint32_t)block_of[(size_t)nd];
                 }
-                top[(size_t)top_index_host(bx, by, bz, top_level)] = (int32_t)e;
+                top[(size_t)top_index_host(bx, by, bz, top_level)] = e;
             }
     (void)depth;
     for (size_t w = 0; w < work.size(); ++w) {

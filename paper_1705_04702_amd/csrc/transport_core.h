@@ -133,9 +133,12 @@ template <typename Real, typename ImgT, int G> struct View {
     int top_level;  // octree: level of the dense top table
     Real lo[3], hi[3], cs[3];
     Real ics[3]; // 1 / cs (FP32 octree steps multiply; FP64 divides)
-    const float *density;
-    const int *node;     // octree: the leaf walk's blocks of 64 entries (top table entries likewise)
-    const int *top;      // octree: the walk's entry for each top-table block
+    const float *density; // Cartesian: per stored cell; octree: per leaf (the walk's entries carry it too)
+    // octree: the leaf walk's blocks of 64 entries and its top table; an entry's
+    // low word is a leaf (bit 31, level, cell) or a block index, a leaf's high
+    // word its density's FP32 bits
+    const unsigned long long *node;
+    const unsigned long long *top;
     long long n_cells;
     // Cartesian storage layout: bricks of 2^bs[0] x 2^bs[1] x 2^bs[2] = 32 cells,
     // nb[] bricks per axis; n_store = cells per wavelength slice incl. padding
@@ -405,7 +408,7 @@ MCRT_HD void begin_march(const View<Real, ImgT, G> &v, Lane<Real> &ln, const Rea
 // several steps can be taken before their density loads complete.  Returns
 // true when the ray leaves the grid after this segment.
 template <typename Real, typename ImgT, int G>
-MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, int &cell, Real &te)
+MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, int &cell, Real &te, float &rho)
 {
     bool exits = false;
     if constexpr (G == kCartesian) {
@@ -459,16 +462,19 @@ MCRT_HD bool geo_step(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, i
         // locate the leaf holding lattice point ci: dense top table, then one
         // load per two levels (blocks of 4 x 4 x 4 sub-cubes)
         const int sh = v.depth - v.top_level;
-        uint32_t e = (uint32_t)v.top[top_index(ln.c0 >> sh, ln.c1 >> sh, ln.c2 >> sh, v.top_level)];
+        unsigned long long e64 = v.top[top_index(ln.c0 >> sh, ln.c1 >> sh, ln.c2 >> sh, v.top_level)];
+        uint32_t e = (uint32_t)e64;
         int lv = v.top_level;
         while (!(e >> 31)) {
             const int s = v.depth - 1 - lv;
             const int i = (((ln.c0 << 1) >> s) & 3) + 4 * (((ln.c1 << 1) >> s) & 3) + 16 * (((ln.c2 << 1) >> s) & 3);
-            e = (uint32_t)v.node[((long long)e << 6) + i];
+            e64 = v.node[((long long)e << 6) + i];
+            e = (uint32_t)e64;
             lv += 2;
         }
         const int level = (int)((e >> 27) & 15u);
         cell = (int)(e & ((1u << 27) - 1));
+        rho = __builtin_bit_cast(float, (uint32_t)(e64 >> 32));
         const int size = 1 << (v.depth - level);
         int o[3];
         Real tn[3];
@@ -551,35 +557,41 @@ MCRT_HD bool apply_segment(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &
     return hit;
 }
 
-// K segments of the march: K geometric steps, then K independent density
-// loads in flight together, then the segments applied in order (the same
-// operations in the same order as one segment at a time).  A Cartesian step
-// is pure arithmetic, so it also runs past the ray's exit (its results are
-// not used) rather than branching; every load reads a valid cell.
+// K segments of the march: K geometric steps, then (Cartesian) K independent
+// density loads in flight together, then the segments applied in order (the
+// same operations in the same order as one segment at a time).  A Cartesian
+// step is pure arithmetic, so it also runs past the ray's exit (its results
+// are not used) rather than branching; every load reads a valid cell.  An
+// octree step's walk entry carries the leaf's density.
 template <int K, typename Real, typename ImgT, int G, typename Sink>
 MCRT_HD void march_batch(const View<Real, ImgT, G> &v, Lane<Real> &ln, Tally &ty, Sink &sink)
 {
     int cell[K];
     Real ts[K], ds[K];
+    float rho[K];
     bool ok[K];
     bool more = true;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         ok[k] = more;
         cell[k] = 0;
+        rho[k] = 0.0f;
         ts[k] = ln.t;
         ds[k] = Real(0);
         if (G == kCartesian || more) {
             Real te;
-            bool exits = geo_step(v, ln, ty, cell[k], te);
+            bool exits = geo_step(v, ln, ty, cell[k], te, rho[k]);
             ds[k] = te - ln.t;
             ln.t = te;
             more = more && !exits;
         }
     }
-    float rho[K];
+    // Cartesian: the densities of the K cells, loaded together; an octree
+    // step found its leaf's density in the walk entry
+    if constexpr (G == kCartesian) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) rho[k] = gload(v.density, ok[k] ? cell[k] : 0);
+        for (int k = 0; k < K; ++k) rho[k] = gload(v.density, ok[k] ? cell[k] : 0);
+    }
     bool stop = false;
 #pragma unroll
     for (int k = 0; k < K; ++k)

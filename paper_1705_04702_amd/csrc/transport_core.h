@@ -22,7 +22,7 @@
 namespace mcrt {
 
 constexpr int kMaxIns = 8;        // instruments per simulation
-constexpr int kMaxLdsLambda = 256; // per-wavelength optics staged in LDS
+constexpr int kMaxLdsLambda = 128; // per-wavelength optics staged in LDS (more: read from global memory)
 
 enum Mode : int {
     kDead = 0,      // no packet (needs a refill)

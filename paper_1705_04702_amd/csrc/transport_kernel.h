@@ -39,13 +39,14 @@ namespace mcrt {
 // open run -- its latest cells that share one line -- are held back while
 // the propagation march goes on, so a run that spans two march iterations
 // still goes out as one request (at most TRK - K slots are held: K new
-// deposits per iteration always fit; TRK == K holds nothing).  A slot holds
-// the cell (u32) and the FP32 absorbed luminosity, which converts to FP64
-// exactly.
-template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
+// deposits per iteration always fit; TRK == K holds nothing).  Without held
+// runs (HOLD false) a tile of TRK >= 2 K slots lets the wave skip the flush
+// of every other iteration (see must_flush).  A slot holds the cell (u32) and
+// the FP32 absorbed luminosity, which converts to FP64 exactly.
+template <bool LEARN, bool HIST, int TRK = 0, int K = 0, bool HOLD = true> struct DevSink {
     static constexpr bool kLearn = LEARN, kHist = HIST;
     static constexpr int kPitch = 64 + (TRK > 0 ? 64 / TRK : 0); // slot-major rows, padded
-    static constexpr bool kHold = TRK > K;
+    static constexpr bool kHold = HOLD && TRK > K;
     static_assert(TRK == 0 || (64 % TRK == 0 && TRK <= 16 && TRK >= K), "slot tile");
     uint32_t *sc = nullptr; // this lane's column of the wave's slot tiles
     float *sv = nullptr;
@@ -74,6 +75,9 @@ template <bool LEARN, bool HIST, int TRK = 0, int K = 0> struct DevSink {
             if (v != 0.0) unsafeAtomicAdd(table + slab + cell, v);
         }
     }
+    // True when some lane of the wave could overflow its slots in the next
+    // march iteration (K more deposits), so the wave must flush now.
+    __device__ __forceinline__ bool must_flush() const { return __ballot(np > TRK - K) != 0; }
     // Issues the slots of closed runs; `hold` keeps the open run for the next
     // iteration (the lane's propagation march goes on).  Every lane posts one
     // word for its ray (wavelength, ring base, slots to issue), laid out so
@@ -292,10 +296,19 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     // the learned proposal (registers, LDS) take one slot per segment -- on
     // the octree's smaller tables the extra issue costs more than the held
     // runs save.
+    //
+    // A flush's atomics stay in the wave's count of outstanding vector memory
+    // operations, which retire in order: the next load the wave waits for
+    // (on the octree, the first walk load of the next iteration) also waits
+    // until every atomic of the flush has been acknowledged by the memory
+    // side.  Octree runs therefore hold no runs but take 16 slots, and the
+    // wave flushes only when a lane could overflow in the next iteration or
+    // when it leaves the march loop: every other iteration.
     constexpr int kK = sizeof(Real) != 4 ? BatchOf<G>::value
                                          : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 4 : 8));
-    constexpr int kTR = sizeof(Real) == 4 ? (G == kCartesian && !LEARN ? 16 : kK) : 0;
-    typedef DevSink<LEARN, HIST, kTR, kK> SinkT;
+    constexpr bool kLazy = sizeof(Real) == 4 && G == kOctree && !LEARN;
+    constexpr int kTR = sizeof(Real) == 4 ? ((G == kCartesian && !LEARN) || kLazy ? 16 : kK) : 0;
+    typedef DevSink<LEARN, HIST, kTR, kK, !kLazy> SinkT;
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
     __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
@@ -376,11 +389,15 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
         // iteration's deposits go out after it
         for (;;) {
             if (ln.marching) march_batch<kK>(v, ln, ty, sink);
-            sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, v.table, v.n_store, s_tc + wave * kTile,
-                       s_tv + wave * kTile, s_word + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
-            if (active == 0 || __popcll(waiting) >= a.threshold) break;
+            const bool leave = active == 0 || __popcll(waiting) >= a.threshold;
+            // a lane's wavelength changes only after the loop: the slots may
+            // wait across iterations, never across a relaunch
+            if (!kLazy || leave || sink.must_flush())
+                sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, v.table, v.n_store,
+                           s_tc + wave * kTile, s_tv + wave * kTile, s_word + wave * 64);
+            if (leave) break;
         }
     }
 

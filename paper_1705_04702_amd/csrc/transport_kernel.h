@@ -301,13 +301,13 @@ __device__ __forceinline__ void transport_body(const TransportArgs<Real, ImgT, G
     // operations, which retire in order: the next load the wave waits for
     // (on the octree, the first walk load of the next iteration) also waits
     // until every atomic of the flush has been acknowledged by the memory
-    // side.  Octree runs therefore hold no runs but take 16 slots, and the
+    // side.  Octree runs therefore hold no runs but take 2 kK slots, and the
     // wave flushes only when a lane could overflow in the next iteration or
     // when it leaves the march loop: every other iteration.
     constexpr int kK = sizeof(Real) != 4 ? BatchOf<G>::value
                                          : (G == kCartesian ? (LEARN ? 4 : 8) : (LEARN ? 4 : 8));
-    constexpr bool kLazy = sizeof(Real) == 4 && G == kOctree && !LEARN;
-    constexpr int kTR = sizeof(Real) == 4 ? ((G == kCartesian && !LEARN) || kLazy ? 16 : kK) : 0;
+    constexpr bool kLazy = sizeof(Real) == 4 && G == kOctree;
+    constexpr int kTR = sizeof(Real) == 4 ? (kLazy ? 2 * kK : (G == kCartesian && !LEARN ? 16 : kK)) : 0;
     typedef DevSink<LEARN, HIST, kTR, kK, !kLazy> SinkT;
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];

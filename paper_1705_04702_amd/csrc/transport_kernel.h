@@ -470,11 +470,14 @@ template <typename Real, typename ImgT>
 __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
                                            const ModelDesc<Real, ImgT> *__restrict__ models)
 {
-    // one deposit slot per segment: the batch's small tables stay in the L2,
-    // where holding runs does not pay for its extra issue
+    // one deposit slot per segment (the batch's small tables stay in the L2,
+    // where holding runs does not pay for its extra issue), 2 kK slots, and a
+    // flush only when a lane could overflow or the wave leaves the march loop
+    // (as in the octree kernels: a flush's atomics delay the next loads the
+    // wave waits for)
     constexpr int kK = sizeof(Real) == 4 ? 8 : BatchOf<0>::value;
-    constexpr int kTR = sizeof(Real) == 4 ? kK : 0;
-    typedef DevSink<false, false, kTR, kK> SinkT;
+    constexpr int kTR = sizeof(Real) == 4 ? 2 * kK : 0;
+    typedef DevSink<false, false, kTR, kK, false> SinkT;
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
     __shared__ float s_tv[kTR ? (kBlock / 64) * kTile : 1];
@@ -569,11 +572,13 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
         }
         for (;;) {
             if (ln.marching) march_batch<kK>(V(), ln, ty, sink);
-            sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, V().table, V().n_store,
-                       s_tc + wave * kTile, s_tv + wave * kTile, s_word + wave * 64);
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
-            if (active == 0 || __popcll(waiting) >= a.threshold) break;
+            const bool leave = active == 0 || __popcll(waiting) >= a.threshold;
+            if (kTR == 0 || leave || sink.must_flush())
+                sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, V().table, V().n_store,
+                           s_tc + wave * kTile, s_tv + wave * kTile, s_word + wave * 64);
+            if (leave) break;
         }
     }
     if (cur_model >= 0) {

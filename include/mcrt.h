@@ -70,7 +70,13 @@ extern "C" {
 #define MCRT_ENONFINITE (-6) /* packets whose luminosity became NaN or infinite were ended
                                 (see stats.nonfinite); the other packets' results are valid */
 
-#define MCRT_FP32 0           /* FP32 transport, FP64 table totals and energy sums */
+/* FP32 transport, FP64 table totals and energy sums.  Luminosities travel
+ * in FP32 and the images are FP32: a wavelength whose packet luminosity
+ * (source or dust luminosity / n_per_lambda) is below FP32's range (the
+ * smallest normal number, 1.2e-38) launches its packets with zero
+ * luminosity and contributes nothing -- the far Wien tail of cold dust
+ * emission, say; the FP64 validation mode keeps it. */
+#define MCRT_FP32 0
 #define MCRT_FP64_VALIDATE 1  /* FP64 throughout, no contraction */
 
 #define MCRT_MAX_INSTRUMENTS 8
@@ -436,7 +442,11 @@ typedef struct {
 } mcrt_dust_params;
 void mcrt_dust_params_default(mcrt_dust_params *p);
 /* Emission of sim's cells from the sum of the absorption tables of
- * absorbed[0 .. n-1] (1 <= n <= 4, results of sim; they must not be running).
+ * absorbed[0 .. n-1] (1 <= n <= 4; results of sim, or of another sim on the
+ * same device whose table has the same layout -- grid, wavelengths and
+ * storage bricks -- such as an FP64 validation run of the same scene, so that
+ * an FP32 sim can emit from a validated absorption; MCRT_EINVAL otherwise;
+ * they must not be running).
  * Computed on the device in FP64 (a fixed-order reduction and scan: the same
  * result on every call); needs the medium's wavelengths.  The handle holds
  * n_lambda x n_cells FP64 running sums on the device until destroyed. */

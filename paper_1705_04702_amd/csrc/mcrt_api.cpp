@@ -1025,8 +1025,23 @@ int mcrt_dust_create(mcrt_sim *sim, const mcrt_result *const *absorbed, int32_t 
     const mcrt_grid *g = m->grid;
     if ((int)m->lambda_um.size() != m->n_lambda)
         return fail(MCRT_EINVAL, "dust_create: the medium was created without wavelengths");
-    for (int i = 0; i < n; ++i)
-        if (!absorbed[i] || absorbed[i]->sim != sim) return fail(MCRT_EINVAL, "dust_create: result of another sim");
+    // results of sim, or of another sim on the device whose table has the
+    // same layout (e.g. an FP64 validation run of the same scene)
+    auto same_layout = [&](const mcrt_sim *o) {
+        if (o == sim) return true;
+        const mcrt_grid *og = o->medium->grid;
+        bool same = o->ctx->device == sim->ctx->device && og->type == g->type && og->n_cells == g->n_cells &&
+                    o->medium->n_lambda == m->n_lambda && o->n_store == sim->n_store;
+        for (int a = 0; a < 3; ++a)
+            same = same && og->n[a] == g->n[a] && o->bs[a] == sim->bs[a] && o->sh[a] == sim->sh[a] &&
+                   o->nb[a] == sim->nb[a];
+        return same;
+    };
+    for (int i = 0; i < n; ++i) {
+        if (!absorbed[i]) return fail(MCRT_EINVAL, "dust_create: NULL result");
+        if (!same_layout(absorbed[i]->sim))
+            return fail(MCRT_EINVAL, "dust_create: result of a sim with another table layout or device");
+    }
     mcrt_dust_params p;
     mcrt_dust_params_default(&p);
     if (params) p = *params;

@@ -114,15 +114,26 @@ def test_dust_errors():
     ctx = mcrt.Context(0)
     sc = _disk()
     s1 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
-    s2 = mcrt.Sim(ctx, sc, mcrt.FP64_VALIDATE)
-    r2 = s2.run(20, seed=0)
-    with pytest.raises(mcrt.MCRTError):
-        s1.dust([r2])                      # result of another sim
+    s2 = mcrt.Sim(ctx, sc, mcrt.FP32)
+    s3 = mcrt.Sim(ctx, scenes.disk(n=(16, 16, 4), n_lambda=6, npix=16, tau_v_faceon=5.0), mcrt.FP64_VALIDATE)
     r1 = s1.run(20, seed=0)
+    r3 = s3.run(20, seed=0)
+    with pytest.raises(mcrt.MCRTError) as ei:
+        s1.dust([r3])                      # result of a sim with another table layout
+    assert ei.value.code == mcrt.EINVAL
+    # a result of another sim with the same layout (here an FP64 run into an
+    # FP32 sim) emits exactly as the sim's own result of the same run would
+    d2 = s2.dust([r1])
+    d1 = s1.dust([r1])
+    np.testing.assert_array_equal(d2.luminosity(), d1.luminosity())
+    np.testing.assert_array_equal(d2.temperature(), d1.temperature())
+    d1.close()
+    d2.close()
     with pytest.raises(mcrt.MCRTError):
         s1.dust([r1], T0=-1.0)
     with pytest.raises(mcrt.MCRTError):
         s1.dust([])
     s1.close()
     s2.close()
+    s3.close()
     ctx.close()

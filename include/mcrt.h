@@ -72,10 +72,11 @@ extern "C" {
 
 /* FP32 transport, FP64 table totals and energy sums.  Luminosities travel
  * in FP32 and the images are FP32: a wavelength whose packet luminosity
- * (source or dust luminosity / n_per_lambda) is below FP32's range (the
- * smallest normal number, 1.2e-38) launches its packets with zero
- * luminosity and contributes nothing -- the far Wien tail of cold dust
- * emission, say; the FP64 validation mode keeps it. */
+ * (source or dust luminosity / n_per_lambda) is below FP32's normal range
+ * (1.2e-38) is carried with fewer significant bits, and below 2^-150
+ * (7e-46) its packets launch with zero luminosity and contribute nothing --
+ * the far Wien tail of cold dust emission, say; the FP64 validation mode
+ * keeps it. */
 #define MCRT_FP32 0
 #define MCRT_FP64_VALIDATE 1  /* FP64 throughout, no contraction */
 

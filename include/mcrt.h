@@ -122,6 +122,10 @@ typedef struct {
                               -6 .. 6; default 0.  The automatic chunk scales with the
                               launch, so a shift tuned on a short trial carries over to
                               the full launch */
+    int32_t deposit_slots; /* FP32 batches (the first simulation's options): deposit slots
+                              per lane in the wave's LDS tile, 8 (the tile is issued
+                              after every march iteration) or 16 (after every other
+                              one); 0 = default (16) */
 } mcrt_options;
 
 /* Batch queue orders (Section 5.2 assigners; Section 7.4 load-balance lesson). */
@@ -281,6 +285,7 @@ typedef struct {
     int32_t from_cache;   /* 1 if the tuner found the setting in its cache */
     double default_ms;    /* trial time of the library's defaults (output of the tuner) */
     int32_t chunk_shift;  /* with chunk = 0: the automatic chunk times 2^chunk_shift (-6 .. 6) */
+    int32_t deposit_slots; /* FP32 batches: deposit tile of 8 or 16 slots per lane; 0 = default */
 } mcrt_tuning;
 
 int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
@@ -289,8 +294,9 @@ int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t);
  * library's defaults unless set), over the chunk as a multiple of the
  * automatic chunk (chunk = 0, chunk_shift -3 .. 3: the automatic chunk
  * scales with the launch, so a setting tuned on a short trial keeps its
- * shape in the full launch), threshold {8..48} and waves per CU
- * {8, 12, 16} with trial runs of trial_packets[i] packets per wavelength of
+ * shape in the full launch), threshold {8..48}, waves per CU
+ * {8, 12, 16} and, for FP32 batches, the deposit tile {8, 16} slots per
+ * lane, with trial runs of trial_packets[i] packets per wavelength of
  * each sim (one sim: the single-model kernel; several: the batched kernel),
  * keeping the fastest; the pick and the defaults are then timed twice more
  * each and the pick is kept only if its best time beats the defaults' (both

@@ -120,7 +120,8 @@ template <typename Real, typename ImgT> struct BatchArgs {
     unsigned long long *counter;
 };
 
-hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream);
+// slots: the deposit tile per lane, 8 or 16
+hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream, int slots);
 
 // learned proposal (proposal.hip)
 struct GradArgs {

@@ -344,6 +344,7 @@ void mcrt_options_default(mcrt_options *opt)
     opt->brick[0] = opt->brick[1] = opt->brick[2] = -1;
     opt->queue_order = MCRT_QUEUE_PAIRED;
     opt->chunk_shift = 0;
+    opt->deposit_slots = 0;
 }
 
 int mcrt_context_create(int device, void *stream, mcrt_context **out)
@@ -628,7 +629,8 @@ int mcrt_sim_create(mcrt_context *ctx, mcrt_medium *medium, mcrt_source *source,
     if (!(o.w_min >= 0.0) || !(o.tau_peel_max > 0.0) || o.event_cap < 1)
         return fail(MCRT_EINVAL, "sim_create: w_min >= 0, tau_peel_max > 0, event_cap >= 1 required");
     if (o.chunk < 0 || o.waves_per_cu < 0 || o.waves_per_cu > 32 || o.threshold < 0 || o.threshold > 64 ||
-        o.chunk_shift < -6 || o.chunk_shift > 6)
+        o.chunk_shift < -6 || o.chunk_shift > 6 || (o.deposit_slots != 0 && o.deposit_slots != 8 &&
+                                                    o.deposit_slots != 16))
         return fail(MCRT_EINVAL, "sim_create: tuning values out of range");
     if (o.queue_order != MCRT_QUEUE_COST && o.queue_order != MCRT_QUEUE_CALLER && o.queue_order != MCRT_QUEUE_PAIRED)
         return fail(MCRT_EINVAL, "sim_create: unknown queue order");
@@ -1351,7 +1353,7 @@ static int batch_impl(mcrt_sim *const *sims, int32_t n, const uint64_t *npl, uin
     HIP_TRY(hipEventCreate(&ev.e1));
     HIP_TRY(hipEventRecord(ev.e0, st));
     hipError_t le;
-    if constexpr (sizeof(Real) == 4) le = launch_batch_f32(a, grid, st);
+    if constexpr (sizeof(Real) == 4) le = launch_batch_f32(a, grid, st, s0->opt.deposit_slots == 8 ? 8 : 16);
     else le = launch_batch_f64(a, grid, st);
     HIP_TRY(le);
     HIP_TRY(hipEventRecord(ev.e1, st));
@@ -1407,12 +1409,14 @@ int mcrt_sim_set_tuning(mcrt_sim *sim, const mcrt_tuning *t)
 {
     if (!sim || !t) return fail(MCRT_EINVAL, "sim_set_tuning: NULL argument");
     if (t->chunk < 0 || t->waves_per_cu <= 0 || t->waves_per_cu > 32 || t->threshold <= 0 || t->threshold > 64 ||
-        t->chunk_shift < -6 || t->chunk_shift > 6)
+        t->chunk_shift < -6 || t->chunk_shift > 6 || (t->deposit_slots != 0 && t->deposit_slots != 8 &&
+                                                       t->deposit_slots != 16))
         return fail(MCRT_EINVAL, "sim_set_tuning: values out of range");
     sim->opt.chunk = t->chunk;
     sim->opt.chunk_shift = t->chunk_shift;
     sim->opt.waves_per_cu = t->waves_per_cu;
     sim->opt.threshold = t->threshold;
+    sim->opt.deposit_slots = t->deposit_slots;
     return MCRT_OK;
 }
 
@@ -1449,8 +1453,9 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
                 if (!bar) continue;
                 *bar = 0;
                 mcrt_tuning t{};
-                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf %lf %d", &t.chunk, &t.waves_per_cu,
-                                               &t.threshold, &t.kernel_ms, &t.default_ms, &t.chunk_shift) >= 4) {
+                if (key == line && std::sscanf(bar + 1, "%d %d %d %lf %lf %d %d", &t.chunk, &t.waves_per_cu,
+                                               &t.threshold, &t.kernel_ms, &t.default_ms, &t.chunk_shift,
+                                               &t.deposit_slots) >= 4) {
                     std::fclose(f);
                     t.from_cache = 1;
                     for (int i = 0; i < n; ++i) {
@@ -1491,7 +1496,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     // automatic chunk), so the search can only keep or beat them
     const mcrt_options &o0 = sims[0]->opt;
     const mcrt_tuning dflt{o0.chunk, o0.waves_per_cu > 0 ? o0.waves_per_cu : 16,
-                           o0.threshold > 0 ? o0.threshold : (n == 1 ? 16 : 24), 0.0, 0, 0.0, o0.chunk_shift};
+                           o0.threshold > 0 ? o0.threshold : (n == 1 ? 16 : 24), 0.0, 0, 0.0, o0.chunk_shift,
+                           o0.deposit_slots > 0 ? o0.deposit_slots : 16};
     mcrt_tuning cur = dflt;
     double ms = 0.0;
     int rc = trial(cur, ms); // warm-up
@@ -1506,13 +1512,15 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     const int shifts[] = {-3, -2, -1, 0, 1, 2, 3};
     const int thresholds[] = {8, 16, 24, 32, 48};
     const int waves[] = {8, 12, 16};
+    const int slots[] = {8, 16}; // the batch kernel's deposit tile (FP32 batches only)
+    const int passes = n > 1 && o0.precision == MCRT_FP32 ? 4 : 3;
     auto same = [](const mcrt_tuning &x, const mcrt_tuning &y) {
         return x.chunk == y.chunk && x.chunk_shift == y.chunk_shift && x.threshold == y.threshold &&
-               x.waves_per_cu == y.waves_per_cu;
+               x.waves_per_cu == y.waves_per_cu && x.deposit_slots == y.deposit_slots;
     };
-    for (int pass = 0; pass < 3 && !rc; ++pass) {
-        const int *vals = pass == 0 ? shifts : pass == 1 ? thresholds : waves;
-        int nv = pass == 0 ? 7 : pass == 1 ? 5 : 3;
+    for (int pass = 0; pass < passes && !rc; ++pass) {
+        const int *vals = pass == 0 ? shifts : pass == 1 ? thresholds : pass == 2 ? waves : slots;
+        int nv = pass == 0 ? 7 : pass == 1 ? 5 : pass == 2 ? 3 : 2;
         for (int k = 0; k < nv; ++k) {
             mcrt_tuning t = cur;
             if (pass == 0) {
@@ -1520,8 +1528,10 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
                 t.chunk_shift = vals[k];
             } else if (pass == 1) {
                 t.threshold = vals[k];
-            } else {
+            } else if (pass == 2) {
                 t.waves_per_cu = vals[k];
+            } else {
+                t.deposit_slots = vals[k];
             }
             if (same(t, cur)) continue;
             rc = trial(t, ms);
@@ -1567,8 +1577,8 @@ int mcrt_autotune(mcrt_sim *const *sims, int32_t n, const uint64_t *trial_packet
     if (cache_path) {
         std::FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s|%d %d %d %.6f %.6f %d\n", key.c_str(), cur.chunk, cur.waves_per_cu, cur.threshold,
-                         cur.kernel_ms, cur.default_ms, cur.chunk_shift);
+            std::fprintf(f, "%s|%d %d %d %.6f %.6f %d %d\n", key.c_str(), cur.chunk, cur.waves_per_cu,
+                         cur.threshold, cur.kernel_ms, cur.default_ms, cur.chunk_shift, cur.deposit_slots);
             std::fclose(f);
         }
     }

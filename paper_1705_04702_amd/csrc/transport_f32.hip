@@ -11,8 +11,9 @@ hipError_t launch_transport_f32o(const TransportArgs<float, float, 1> &a, int gr
 {
     return launch_transport_impl<float, float, 1>(a, grid, stream);
 }
-hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream)
+hipError_t launch_batch_f32(const BatchArgs<float, float> &a, int grid, hipStream_t stream, int slots)
 {
-    return launch_batch_impl<float, float>(a, grid, stream);
+    if (slots == 8) return launch_batch_impl<float, float, 8>(a, grid, stream);
+    return launch_batch_impl<float, float, 16>(a, grid, stream);
 }
 } // namespace mcrt

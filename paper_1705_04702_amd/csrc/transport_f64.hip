@@ -14,6 +14,6 @@ hipError_t launch_transport_f64o(const TransportArgs<double, double, 1> &a, int 
 }
 hipError_t launch_batch_f64(const BatchArgs<double, double> &a, int grid, hipStream_t stream)
 {
-    return launch_batch_impl<double, double>(a, grid, stream);
+    return launch_batch_impl<double, double, 0>(a, grid, stream);
 }
 } // namespace mcrt

@@ -466,17 +466,20 @@ __device__ __forceinline__ void flush_tally(Tally &ty, double *energy, unsigned 
 // model's parameters are wave-uniform, and drains its lanes before it
 // switches to a chunk of another model (tallies are flushed at the switch).
 // The model index is the fourth word of every packet's Philox counter.
-template <typename Real, typename ImgT>
+template <typename Real, typename ImgT, int SLOTS>
 __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
                                            const ModelDesc<Real, ImgT> *__restrict__ models)
 {
     // one deposit slot per segment (the batch's small tables stay in the L2,
-    // where holding runs does not pay for its extra issue), 2 kK slots, and a
-    // flush only when a lane could overflow or the wave leaves the march loop
-    // (as in the octree kernels: a flush's atomics delay the next loads the
-    // wave waits for)
+    // where holding runs does not pay for its extra issue).  SLOTS (FP32) is
+    // the tile per lane, a tuning choice: kK slots, issued after every march
+    // iteration, or 2 kK, issued only when a lane could overflow or the wave
+    // leaves the march loop (as in the octree kernels: a flush's atomics
+    // delay the next loads the wave waits for)
     constexpr int kK = sizeof(Real) == 4 ? 8 : BatchOf<0>::value;
-    constexpr int kTR = sizeof(Real) == 4 ? 2 * kK : 0;
+    constexpr int kTR = sizeof(Real) == 4 ? SLOTS : 0;
+    static_assert(sizeof(Real) != 4 || SLOTS == kK || SLOTS == 2 * kK, "deposit tile");
+    constexpr bool kLazyB = kTR == 2 * kK;
     typedef DevSink<false, false, kTR, kK, false> SinkT;
     constexpr int kTile = kTR ? kTR * SinkT::kPitch : 1;
     __shared__ uint32_t s_tc[kTR ? (kBlock / 64) * kTile : 1];
@@ -575,7 +578,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
             unsigned long long waiting = __ballot(!ln.marching && (ln.mode != kDead || !exhausted));
             unsigned long long active = __ballot(ln.marching);
             const bool leave = active == 0 || __popcll(waiting) >= a.threshold;
-            if (kTR == 0 || leave || sink.must_flush())
+            if (!kLazyB || leave || sink.must_flush())
                 sink.flush(lane, ln.marching && ln.mode == kProp, (int)ln.lam, V().table, V().n_store,
                            s_tc + wave * kTile, s_tv + wave * kTile, s_word + wave * 64);
             if (leave) break;
@@ -589,24 +592,25 @@ __device__ __forceinline__ void batch_body(const BatchArgs<Real, ImgT> &a,
 
 // FP32: four waves per SIMD (128 VGPRs, a few registers spilled): the
 // event-heavy batch gains more from the extra wave than the spills cost.
-template <typename ImgT>
+template <typename ImgT, int SLOTS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 batch_transport_kernel_f32(BatchArgs<float, ImgT> a, const ModelDesc<float, ImgT> *__restrict__ models)
 {
-    batch_body<float, ImgT>(a, models);
+    batch_body<float, ImgT, SLOTS>(a, models);
 }
 
 template <typename ImgT>
 __global__ void __launch_bounds__(kBlock) batch_transport_kernel_f64(BatchArgs<double, ImgT> a, const ModelDesc<double, ImgT> *__restrict__ models)
 {
-    batch_body<double, ImgT>(a, models);
+    batch_body<double, ImgT, 0>(a, models);
 }
 
-template <typename Real, typename ImgT>
+template <typename Real, typename ImgT, int SLOTS>
 hipError_t launch_batch_impl(const BatchArgs<Real, ImgT> &a, int grid, hipStream_t stream)
 {
     if constexpr (sizeof(Real) == 4)
-        hipLaunchKernelGGL(batch_transport_kernel_f32<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a, a.models);
+        hipLaunchKernelGGL((batch_transport_kernel_f32<ImgT, SLOTS>), dim3(grid), dim3(kBlock), 0, stream, a,
+                           a.models);
     else
         hipLaunchKernelGGL(batch_transport_kernel_f64<ImgT>, dim3(grid), dim3(kBlock), 0, stream, a, a.models);
     return hipGetLastError();

@@ -64,6 +64,7 @@ class Options(ctypes.Structure):
         ("brick", ctypes.c_int32 * 3),
         ("queue_order", ctypes.c_int32),
         ("chunk_shift", ctypes.c_int32),
+        ("deposit_slots", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,7 @@ STAT_FIELDS = ["packets", "events", "prop_cells", "locate_cells", "peel_cells", 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("from_cache", ctypes.c_int32), ("default_ms", ctypes.c_double),
-                ("chunk_shift", ctypes.c_int32)]
+                ("chunk_shift", ctypes.c_int32), ("deposit_slots", ctypes.c_int32)]
 
 
 class MlpDesc(ctypes.Structure):
@@ -469,8 +470,9 @@ class Sim:
                                            int(max_events), result.h, ctypes.byref(h)), allow=(ELIMIT, ENONFINITE))
         return Histories(h, self.ctx)
 
-    def set_tuning(self, chunk: int, waves_per_cu: int, threshold: int):
-        t = Tuning(chunk, waves_per_cu, threshold, 0.0, 0)
+    def set_tuning(self, chunk: int, waves_per_cu: int, threshold: int, chunk_shift: int = 0,
+                   deposit_slots: int = 0):
+        t = Tuning(chunk, waves_per_cu, threshold, 0.0, 0, 0.0, chunk_shift, deposit_slots)
         _check(lib().mcrt_sim_set_tuning(self.h, ctypes.byref(t)))
 
     def new_result(self) -> Result:
@@ -702,7 +704,8 @@ def autotune(sims: Sequence["Sim"], trial_packets: Sequence[int], seed: int = 0,
     t = Tuning()
     _check(lib().mcrt_autotune(_handles(sims), n, tp, int(seed),
                                cache_path.encode() if cache_path else None, ctypes.byref(t)))
-    return {"chunk": t.chunk, "chunk_shift": t.chunk_shift, "waves_per_cu": t.waves_per_cu,
+    return {"chunk": t.chunk, "chunk_shift": t.chunk_shift, "deposit_slots": t.deposit_slots,
+            "waves_per_cu": t.waves_per_cu,
             "threshold": t.threshold, "kernel_ms": t.kernel_ms, "default_ms": t.default_ms,
             "from_cache": bool(t.from_cache)}
 

@@ -40,6 +40,7 @@ def test_host_side_options_and_errors():
     o = mcrt.default_options()
     assert o.precision == mcrt.FP32 and o.w_min == 1e-6 and o.event_cap == 10000
     assert o.tau_peel_max == math.inf and o.top_level == -1 and o.queue_order == mcrt.QUEUE_PAIRED
+    assert o.chunk_shift == 0 and o.deposit_slots == 0
     with pytest.raises(TypeError):  # a misspelt option is an error, not a silent no-op
         mcrt.default_options(treshold=8)
     L = mcrt.lib()

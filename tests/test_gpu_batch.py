@@ -121,12 +121,13 @@ def test_autotune_and_cache(ctx, tmp_path):
         assert not t1["from_cache"]
         assert t1["chunk"] in (0, 256, 512, 1024, 2048, 4096, 8192, 16384) and t1["threshold"] in (8, 16, 24, 32, 48)
         assert t1["waves_per_cu"] in (8, 12, 16) and t1["kernel_ms"] > 0
+        assert t1["deposit_slots"] in (8, 16)  # the FP32 batch's deposit tile is a tuned dimension
         # the search starts from the library's defaults and keeps its pick only
         # if the pick's confirmed time beats the defaults' confirmed time
         assert 0 < t1["kernel_ms"] <= t1["default_ms"]
         t2 = mcrt.autotune(sims, [1] * len(sims), seed=3, cache_path=cache)
-        assert t2["from_cache"] and (t2["chunk"], t2["threshold"], t2["waves_per_cu"]) == \
-            (t1["chunk"], t1["threshold"], t1["waves_per_cu"])
+        assert t2["from_cache"] and (t2["chunk"], t2["threshold"], t2["waves_per_cu"], t2["deposit_slots"]) == \
+            (t1["chunk"], t1["threshold"], t1["waves_per_cu"], t1["deposit_slots"])
         assert open(cache).read().count("|") == 1
         # single-model tuning uses the single-model kernel
         t3 = mcrt.autotune(sims[:1], [max(1, packets[0] // 4)], seed=3)

@@ -20,6 +20,9 @@ from test_gpu_parity import say
 pytestmark = pytest.mark.gpu
 
 TUNINGS = [dict(), dict(chunk=16, threshold=4, waves_per_cu=4), dict(chunk=512, threshold=48, waves_per_cu=16)]
+# the batch kernel's two deposit tiles: 8 slots per lane issued every march
+# iteration, 16 every other one
+BATCH_TUNINGS = TUNINGS + [dict(deposit_slots=8), dict(deposit_slots=8, chunk=16, threshold=4, waves_per_cu=4)]
 
 
 @pytest.fixture(scope="module")
@@ -73,14 +76,14 @@ def test_fp32_learned_octree_table_sum_equals_absorbed(ctx, tune):
     prop.close()
 
 
-@pytest.mark.parametrize("tune", range(len(TUNINGS)))
+@pytest.mark.parametrize("tune", range(len(BATCH_TUNINGS)))
 def test_fp32_batch_table_sums_equal_absorbed(ctx, tune):
     models = scenes.batch(256, seed=4)[::32]
-    sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32, **TUNINGS[tune]) for m in models]
+    sims = [mcrt.Sim(ctx, m.scene, mcrt.FP32, **BATCH_TUNINGS[tune]) for m in models]
     res = [s.new_result() for s in sims]
     mcrt.batch_run_into(sims, res, [5000] * len(sims), seed=6)
     for i, r in enumerate(res):
-        _check(r, f"batch model {i} {TUNINGS[tune]}")
+        _check(r, f"batch model {i} {BATCH_TUNINGS[tune]}")
         r.close()
     for s in sims:
         s.close()

@@ -460,7 +460,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="disk")
+    ap.add_argument("--workload", default="disk",
+                    choices=("disk", "sphere", "torus", "batch", "torus-learned", "disk-dust"))
     ap.add_argument("--n-per-lambda", type=int, default=0, help="0 = the workload's own")
     ap.add_argument("--autotune", action="store_true", help="tune the queue before timing (batch: always)")
     ap.add_argument("--no-autotune", action="store_true", help="batch: time the library's default queue")

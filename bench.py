@@ -262,7 +262,7 @@ def learned_vs_plain(args):
         """Runs ids [first, first + count) in blocks; returns the image cube and
         the summed kernel time."""
         count = n_per_lambda - first if count is None else count
-        sim.set_proposal(prop if learned else None, 0.2)
+        sim.set_proposal(prop if learned else None, args.alpha)
         res = sim.new_result()
         block = 3_000_000
         kms = 0.0
@@ -305,7 +305,7 @@ def learned_vs_plain(args):
                           "instrument) with the learned vMF-mixture direction proposal",
               "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
               "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
-              "alpha": 0.2, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+              "alpha": args.alpha, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
               "max_events": args.max_events, "tau_peel_max": sc.tau_peel_max}
     cmp = {"rms_learned": rms_l, "rms_plain": rms_p, "t_learned_s": t_learned,
            "t_plain_s": t_plain, "rms2_t_learned": rms_l ** 2 * t_learned,
@@ -485,6 +485,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=2, help="torus-learned: training epochs")
     ap.add_argument("--batch", type=int, default=16384, help="torus-learned: samples per Adam step")
     ap.add_argument("--lr", type=float, default=1e-3, help="torus-learned: Adam learning rate")
+    ap.add_argument("--alpha", type=float, default=0.1,
+                    help="torus-learned: weight of the HG component in the defensive mixture")
     ap.add_argument("--max-events", type=int, default=16, help="torus-learned: recorded events per packet")
     ap.add_argument("--no-learned", action="store_true",
                     help="default line: skip the learned-vs-plain comparison on the torus")

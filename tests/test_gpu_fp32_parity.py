@@ -22,8 +22,9 @@ instruments (face-on and edge-on read column maps, 60 deg marches), on 4 of
 its wavelengths; the clumpy torus at full size (2.24e6 leaves, 1024^2) on 8
 of its wavelengths; a subset of the 256-model batch in one batched launch;
 the learned proposal (MFMA network) on the full torus against the oracle's
-FP64 network with the same parameters; dust packets of a disk (the dust
-emission phase) emitted from the same absorption as the oracle's.
+FP64 network with the same parameters; the learned proposal's Cartesian kernel on a
+disk; dust packets of a disk (the dust emission phase) emitted from the
+same absorption as the oracle's.
 """
 import json
 import math
@@ -250,3 +251,19 @@ def test_dust_packets_fp32_per_cell_and_pixel(ctx):
         h.close()
     sim32.close()
     sim64.close()
+
+
+def test_learned_disk_fp32_per_cell_and_pixel(ctx):
+    """The learned proposal's Cartesian FP32 kernel (the torus test above
+    covers the octree one) on a disk with all three instruments (two column
+    maps, one marched), against the oracle's FP64 network with the same
+    parameters, per cell and pixel at 3 sigma of the learned run's noise."""
+    sc = scenes.disk(n=(32, 32, 16), n_lambda=4, npix=32)
+    N = 20_000
+    theta = _learned_params(11)
+    say(f"fp32 parity learned disk 32x32x16, 4 wavelengths, {N} ids each")
+    g = _gpu(ctx, sc, N, seed=15, theta=theta)
+    o = oracle_par.run(sc, N, seed=15, moments=True, mlp=theta)
+    eo = o["energy"]
+    report("learned disk 32x32x16, 3 x 32^2 (i = 0/60/90), 4 wavelengths", g, o, N, balance_tol=0.05,
+           extra={"learned_energy_balance_oracle": float(abs(eo[0] - eo[1] - eo[2] - eo[3]) / eo[0])})

@@ -23,7 +23,8 @@ its wavelengths; the clumpy torus at full size (2.24e6 leaves, 1024^2) on 8
 of its wavelengths; a subset of the 256-model batch in one batched launch;
 the learned proposal (MFMA network) on the full torus against the oracle's
 FP64 network with the same parameters; the learned proposal's Cartesian kernel on a
-disk; dust packets of a disk (the dust emission phase) emitted from the
+disk; history-recording runs (training data collection) on a disk and a
+torus; dust packets of a disk (the dust emission phase) emitted from the
 same absorption as the oracle's.
 """
 import json
@@ -267,3 +268,26 @@ def test_learned_disk_fp32_per_cell_and_pixel(ctx):
     eo = o["energy"]
     report("learned disk 32x32x16, 3 x 32^2 (i = 0/60/90), 4 wavelengths", g, o, N, balance_tol=0.05,
            extra={"learned_energy_balance_oracle": float(abs(eo[0] - eo[1] - eo[2] - eo[3]) / eo[0])})
+
+
+@pytest.mark.parametrize("name", ["disk", "torus"])
+def test_history_runs_fp32_per_cell_and_pixel(ctx, name):
+    """A history-recording run (the training data collection) is the plain
+    estimator run by the kernels' history variants (Cartesian: held deposit
+    runs; octree: flushes every other iteration): its FP32 table and images
+    against the oracle's plain run, per cell and pixel."""
+    if name == "disk":
+        sc = scenes.disk(n=(32, 32, 16), n_lambda=4, npix=32)
+    else:
+        sc = scenes.torus(5, 4, 3, 32, n_clumps=25, tau_eq=8.0)
+    N = 20_000
+    sim = mcrt.Sim(ctx, sc, mcrt.FP32)
+    res = sim.new_result()
+    say(f"fp32 parity history run {name}, {N} ids per wavelength")
+    h = sim.collect(res, N, seed=16, max_events=16)
+    g = {"table": res.table(), "images": res.images(), "energy": res.energy()}
+    o = oracle_par.run(sc, N, seed=16, moments=True)
+    report(f"history-recording run, {name} ({sc.name})", g, o, N)
+    h.close()
+    res.close()
+    sim.close()

@@ -318,7 +318,8 @@ def learned_vs_plain(args):
            "energy_balance_learned":
                abs(e_learned[0] - e_learned[1] - e_learned[2] - e_learned[3]) / e_learned[0],
            "workload": config["workload"], "history_packets": n_hist * nl, "learned_packets": n_learn * nl,
-           "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl}
+           "reference_packets": n_ref * nl, "plain_packets_equal_time": n_plain * nl,
+           "alpha": args.alpha, "epochs": args.epochs}
     prop.close()
     sim.close()
     return n_learn * nl / t_learned, t_learned, cmp, config
